@@ -1,0 +1,231 @@
+/*
+ * cayleygrowth.h -- C ABI of libcayleygrowth.so: growth of permutation-group
+ * Cayley graphs by layered breadth-first search on an MI355X (gfx950).
+ *
+ * What is computed (paper, section "Reminder on Cayley graphs, diameters,
+ * growth", definition of Growth): for the graph whose vertices are the
+ * states reachable from a start vector and whose edges join v and v.g for
+ * every generator g, gamma(m) is the number of vertices at shortest-path
+ * distance m from the start. The diameter (from the start) is the number of
+ * layers minus one (same section). Generators are permutations in one-line
+ * notation, 0-based (section "Examples and Tutorials"; explicit 0-based
+ * definitions in section "Sheveleva2 and Koltsov3involutions").
+ *
+ * Action convention: gather, the neighbour t of state s under g has
+ * t[i] = s[g[i]]. Layer SIZES do not depend on this choice; exported layer
+ * CONTENTS do.
+ *
+ * Every call is exact integer work: layer counts are 64-bit and bit-exact.
+ *
+ * Threading: every entry point may be called from several host threads;
+ * each call (or queue) owns its device buffers and stream. No C++
+ * exception crosses this boundary.
+ *
+ * Memory: input pointers are host pointers borrowed for the duration of the
+ * call (the queue copies what it needs before cg_queue_submit returns).
+ * Output arrays are caller-owned host memory. Device memory is owned by the
+ * library and released before each call returns (queue: when a job retires).
+ */
+#ifndef CAYLEYGROWTH_H
+#define CAYLEYGROWTH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define CG_OK 0            /* complete: an empty next layer was reached      */
+#define CG_TRUNCATED 1     /* a stop rule ended the search (max_layers,
+                              max_frontier); the last layer is non-empty     */
+#define CG_PENDING 2       /* queue: the job has not finished yet            */
+#define CG_E_INVAL (-1)    /* bad argument: n outside 1..16, n_gens < 1, a
+                              generator row that is not a permutation of
+                              0..n-1, max_layers < 1, NULL pointer, start
+                              entry > 15                                      */
+#define CG_E_NOMEM (-2)    /* device or host memory exhausted                */
+#define CG_E_DEVICE (-3)   /* HIP error or a kernel-reported failure         */
+#define CG_E_UNSUPPORTED (-4) /* generating set not closed under inverses
+                              and CG_ALLOW_DIRECTED not given                */
+#define CG_E_BUSY (-5)     /* queue full                                     */
+#define CG_E_CANCELLED (-6)/* job cancelled before it finished               */
+#define CG_E_TIMEOUT (-7)  /* cg_queue_wait timed out (job still running)     */
+
+/* ---- job flags ----------------------------------------------------------- */
+#define CG_KEEP_ALL_LAYERS 0x1u  /* keep every layer resident on the device
+                                    (otherwise only layers d-1, d, d+1)     */
+#define CG_ALLOW_DIRECTED 0x2u   /* accept sets not closed under inverses;
+                                    removes every earlier layer, not just
+                                    d-1 and d (implies keeping all layers)  */
+#define CG_START_STATE 0x4u      /* start from job.start instead of the
+                                    identity (Schreier coset graphs: a start
+                                    vector with repeated entries)            */
+#define CG_PROFILE 0x8u          /* record per-kernel HIP-event timings into
+                                    cg_result_t.kstats                        */
+
+/*
+ * A growth job.
+ *   n            entries per state, 1..16 (each entry is packed in 4 bits)
+ *   gens         n_gens rows of n bytes, row-major; row g holds the one-line
+ *                images g[0..n-1]. Duplicate rows and the identity are
+ *                allowed and ignored (they do not change any layer).
+ *   n_gens       number of rows, >= 1
+ *   max_layers   capacity of the caller's layer_sizes array, >= 1; at most
+ *                this many layers (including layer 0) are computed
+ *   max_frontier 0 = none; otherwise the first layer whose size is strictly
+ *                greater than this is recorded and not expanded
+ *   flags        CG_* job flags
+ *   start        n bytes with entries 0..15 when CG_START_STATE is set,
+ *                else ignored (NULL allowed)
+ *   layers_out   optional host buffer (NULL = none): receives every
+ *                recorded layer's states, layer after layer, each layer in
+ *                increasing lexicographic order, n bytes per state
+ *   layers_out_cap  capacity of layers_out in states; states beyond it are
+ *                not written (the sizes still count them)
+ */
+typedef struct cg_job {
+    int n;
+    const uint8_t *gens;
+    int n_gens;
+    int max_layers;
+    uint64_t max_frontier;
+    uint32_t flags;
+    const uint8_t *start;
+    uint8_t *layers_out;
+    uint64_t layers_out_cap;
+} cg_job_t;
+
+/* Per-kernel timing record (filled when CG_PROFILE is set). */
+typedef struct cg_kstat {
+    char name[32];
+    uint64_t launches;
+    double total_ms;   /* sum of HIP-event durations over all launches      */
+    double alg_bytes;  /* algorithmic HBM bytes over all launches (what the
+                          method itself must read and write)                */
+    double items;      /* keys processed over all launches                   */
+} cg_kstat_t;
+
+#define CG_KSTAT_MAX 8
+
+/*
+ * Result of a job. layer_sizes is a caller-owned array of job.max_layers
+ * entries; entries after the last recorded layer are set to 0.
+ *   status          CG_OK, CG_TRUNCATED or a negative error code
+ *   num_layers      recorded layers (diameter from the start = num_layers-1
+ *                   when status == CG_OK)
+ *   states_expanded sum of the sizes of the layers that were expanded
+ *   candidates      neighbours generated (states_expanded x distinct gens)
+ *   t_submit, t_admit, t_done   host monotonic seconds (queue jobs; the
+ *                   plain calls set all three around the call)
+ *   device_ms       HIP-event time from the first to the last kernel
+ */
+typedef struct cg_result {
+    int status;
+    int num_layers;
+    uint64_t *layer_sizes;
+    uint64_t states_expanded;
+    uint64_t candidates;
+    double t_submit, t_admit, t_done;
+    double device_ms;
+    int n_kstats;
+    cg_kstat_t kstats[CG_KSTAT_MAX];
+} cg_result_t;
+
+/*
+ * cg_growth -- growth from the identity (definition of Growth).
+ * out_layer_sizes: caller-owned, max_layers entries, zero-filled after the
+ * last layer. Returns CG_OK, CG_TRUNCATED, or a negative error. The set
+ * must be closed under inverses (paper: the standard undirected case of the
+ * section "Largest diameters found (and known) for n <= 15").
+ */
+int cg_growth(int n, const uint8_t *gens, int n_gens, int max_layers,
+              uint64_t *out_layer_sizes);
+
+/*
+ * cg_growth_ex -- the full job interface. res->layer_sizes must point to
+ * job->max_layers entries. stream: a hipStream_t to run on, or NULL for a
+ * stream owned by the call. Returns res->status.
+ */
+int cg_growth_ex(const cg_job_t *job, cg_result_t *res, void *stream);
+
+/*
+ * Batch options.
+ *   stream         hipStream_t or NULL
+ *   max_active     most jobs advanced together in one super-step (0 = auto)
+ *   hbm_budget_bytes  device bytes the batch may use (0 = auto: 80% of free)
+ *   tune           1 = let the autotuner choose tile and bucket sizes
+ */
+typedef struct cg_batch_opts {
+    void *stream;
+    int max_active;
+    uint64_t hbm_budget_bytes;
+    int tune;
+} cg_batch_opts_t;
+
+/*
+ * cg_growth_batch -- many independent jobs advanced together: their states
+ * carry the job's index in the high key bits, so one expand, sort, unique,
+ * set difference and compaction per super-step serves every active job.
+ * Each result equals that job's cg_growth_ex result bit for bit. Workload
+ * shape: the paper's searches over many generating sets (section "Largest
+ * diameters found (and known) for n <= 15"). results[i].layer_sizes must
+ * point to jobs[i].max_layers entries. opts may be NULL. Jobs must not set
+ * CG_ALLOW_DIRECTED, CG_KEEP_ALL_LAYERS or layers_out (CG_E_INVAL).
+ * Returns CG_OK when every job ran (see each results[i].status), or a
+ * negative error for the whole batch.
+ */
+int cg_growth_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results,
+                    const cg_batch_opts_t *opts);
+
+/* ---- serving: a request queue with continuous batching ------------------ */
+typedef struct cg_queue cg_queue_t;
+
+/*
+ *   hbm_budget_bytes  device bytes the active jobs may use together
+ *                     (0 = 80% of free memory at creation)
+ *   max_active        most jobs on the device at once (0 = 256)
+ *   max_queued        most jobs waiting (0 = 65536); beyond it CG_E_BUSY
+ */
+typedef struct cg_queue_opts {
+    uint64_t hbm_budget_bytes;
+    int max_active;
+    int max_queued;
+} cg_queue_opts_t;
+
+/* Creates the queue and its engine thread; NULL on failure (cg_last_error). */
+cg_queue_t *cg_queue_create(const cg_queue_opts_t *opts);
+
+/*
+ * Enqueue a job. The job's gens/start are copied before return; res_slot
+ * and res_slot->layer_sizes must stay valid until the job is done,
+ * cancelled or the queue is destroyed. *ticket receives the job's id.
+ * Returns CG_OK, CG_E_INVAL or CG_E_BUSY.
+ */
+int cg_queue_submit(cg_queue_t *q, const cg_job_t *job, cg_result_t *res_slot,
+                    uint64_t *ticket);
+
+/* CG_OK (done; res_slot filled), CG_PENDING, or the job's negative status. */
+int cg_queue_poll(cg_queue_t *q, uint64_t ticket);
+
+/* Waits up to timeout_us (< 0 = forever). Returns like cg_queue_poll, or
+   CG_E_TIMEOUT. */
+int cg_queue_wait(cg_queue_t *q, uint64_t ticket, int64_t timeout_us);
+
+/* Cancels a queued or running job; it retires with CG_E_CANCELLED at the
+   next super-step boundary. Returns CG_OK or CG_E_INVAL (unknown ticket). */
+int cg_queue_cancel(cg_queue_t *q, uint64_t ticket);
+
+/* Cancels what is left, drains the engine thread, frees everything. */
+void cg_queue_destroy(cg_queue_t *q);
+
+/* ---- errors -------------------------------------------------------------- */
+const char *cg_strerror(int code);
+/* Detail string of the last failure on the calling thread ("" if none). */
+const char *cg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAYLEYGROWTH_H */

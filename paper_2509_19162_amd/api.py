@@ -1,0 +1,224 @@
+"""Python binding of libcayleygrowth.so: argument marshalling only.
+
+Every step of the growth computation runs in the library's HIP kernels;
+this module converts Python/numpy arguments into the C structures and
+raises on negative status codes. PyTorch is used only to hand the library a
+stream (``stream=torch.cuda.current_stream()``) when the caller wants one.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import _native as N
+
+
+class CGError(RuntimeError):
+    def __init__(self, code: int, detail: str):
+        self.code = code
+        msg = N.lib().cg_strerror(code).decode()
+        super().__init__(f"{msg} ({code}): {detail}" if detail else f"{msg} ({code})")
+
+
+@dataclass
+class GrowthResult:
+    status: int
+    sizes: List[int]
+    states_expanded: int
+    candidates: int
+    device_ms: float
+    t_submit: float = 0.0
+    t_admit: float = 0.0
+    t_done: float = 0.0
+    kstats: Dict[str, Dict[str, float]] = field(default_factory=dict)
+    layers: Optional[List[np.ndarray]] = None
+
+    @property
+    def complete(self) -> bool:
+        return self.status == N.CG_OK
+
+    @property
+    def diameter(self) -> int:
+        return len(self.sizes) - 1
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(getattr(stream, "cuda_stream"))  # torch.cuda.Stream
+
+
+def _gens_array(n: int, gens: Sequence[Sequence[int]]) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(gens, dtype=np.uint8).reshape(-1, n))
+    return a
+
+
+def _ptr(a: Optional[np.ndarray], t=N.u8p):
+    if a is None:
+        return None
+    return a.ctypes.data_as(t)
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise CGError(rc, N.lib().cg_last_error().decode())
+    return rc
+
+
+class _JobHolder:
+    """Keeps the numpy buffers of a CgJob alive."""
+
+    def __init__(self, n, gens, max_layers, max_frontier, flags, start, export_cap):
+        self.n = n
+        self.gens = _gens_array(n, gens)
+        self.start = None if start is None else np.ascontiguousarray(np.asarray(start, dtype=np.uint8))
+        if self.start is not None:
+            flags |= N.CG_START_STATE
+        self.export = None
+        if export_cap:
+            self.export = np.zeros((export_cap, n), dtype=np.uint8)
+        self.sizes = np.zeros(max_layers, dtype=np.uint64)
+        self.job = N.CgJob(
+            n, _ptr(self.gens), self.gens.shape[0], max_layers, max_frontier or 0, flags,
+            _ptr(self.start), _ptr(self.export), export_cap or 0,
+        )
+        self.res = N.CgResult()
+        self.res.layer_sizes = self.sizes.ctypes.data_as(N.u64p)
+
+    def result(self) -> GrowthResult:
+        r = self.res
+        sizes = [int(x) for x in self.sizes[: r.num_layers]] if r.status >= 0 else []
+        ks = {}
+        for i in range(r.n_kstats):
+            k = r.kstats[i]
+            ks[k.name.decode()] = {
+                "launches": int(k.launches),
+                "total_ms": float(k.total_ms),
+                "alg_bytes": float(k.alg_bytes),
+                "items": float(k.items),
+            }
+        layers = None
+        if self.export is not None and r.status >= 0:
+            layers = []
+            off = 0
+            for s in sizes:
+                layers.append(self.export[off: off + s])
+                off += s
+        return GrowthResult(
+            r.status, sizes, int(r.states_expanded), int(r.candidates), float(r.device_ms),
+            float(r.t_submit), float(r.t_admit), float(r.t_done), ks, layers,
+        )
+
+
+def growth(n: int, gens: Sequence[Sequence[int]], max_layers: int = 256,
+           max_frontier: Optional[int] = None) -> List[int]:
+    """Growth (layer sizes) of the Cayley graph from the identity
+    (``cg_growth``). Raises CGError on failure."""
+    g = _gens_array(n, gens)
+    sizes = np.zeros(max_layers, dtype=np.uint64)
+    if max_frontier:
+        return growth_ex(n, gens, max_layers=max_layers, max_frontier=max_frontier).sizes
+    rc = _check(N.lib().cg_growth(n, _ptr(g), g.shape[0], max_layers, sizes.ctypes.data_as(N.u64p)))
+    nz = np.nonzero(sizes)[0]
+    last = int(nz[-1]) + 1 if len(nz) else 0
+    del rc
+    return [int(x) for x in sizes[:last]]
+
+
+def growth_ex(n: int, gens: Sequence[Sequence[int]], max_layers: int = 256,
+              max_frontier: Optional[int] = None, start: Optional[Sequence[int]] = None,
+              keep_all_layers: bool = False, allow_directed: bool = False, profile: bool = False,
+              export_layers: int = 0, stream=None) -> GrowthResult:
+    """The full job interface (``cg_growth_ex``).
+
+    ``export_layers``: capacity (in states) of the layer-content export; the
+    result's ``layers`` then lists each layer's states in increasing
+    lexicographic order as ``uint8[count, n]`` arrays.
+    """
+    flags = 0
+    if keep_all_layers:
+        flags |= N.CG_KEEP_ALL_LAYERS
+    if allow_directed:
+        flags |= N.CG_ALLOW_DIRECTED
+    if profile:
+        flags |= N.CG_PROFILE
+    h = _JobHolder(n, gens, max_layers, max_frontier, flags, start, export_layers)
+    _check(N.lib().cg_growth_ex(ctypes.byref(h.job), ctypes.byref(h.res), _stream_handle(stream)))
+    return h.result()
+
+
+def growth_batch(jobs, max_layers: int = 256, max_active: int = 0, budget_bytes: int = 0,
+                 tune: bool = True, stream=None) -> List[GrowthResult]:
+    """Many independent jobs in shared super-steps (``cg_growth_batch``).
+
+    ``jobs``: a list of ``(n, gens)`` or ``(n, gens, max_frontier)``.
+    """
+    holders = []
+    for j in jobs:
+        n, gens = j[0], j[1]
+        mf = j[2] if len(j) > 2 else None
+        holders.append(_JobHolder(n, gens, max_layers, mf, 0, None, 0))
+    JobArr = N.CgJob * len(holders)
+    ResArr = N.CgResult * len(holders)
+    ja = JobArr(*[h.job for h in holders])
+    ra = ResArr()
+    for i, h in enumerate(holders):
+        ra[i].layer_sizes = h.sizes.ctypes.data_as(N.u64p)
+    opts = N.CgBatchOpts(_stream_handle(stream), max_active, budget_bytes, 1 if tune else 0)
+    _check(N.lib().cg_growth_batch(len(holders), ja, ra, ctypes.byref(opts)))
+    out = []
+    for i, h in enumerate(holders):
+        h.res = ra[i]
+        out.append(h.result())
+    return out
+
+
+class GrowthQueue:
+    """Request queue with continuous batching (``cg_queue_*``)."""
+
+    def __init__(self, budget_bytes: int = 0, max_active: int = 0, max_queued: int = 0):
+        opts = N.CgQueueOpts(budget_bytes, max_active, max_queued)
+        self._q = N.lib().cg_queue_create(ctypes.byref(opts))
+        if not self._q:
+            raise CGError(N.CG_E_DEVICE, N.lib().cg_last_error().decode())
+        self._jobs: Dict[int, _JobHolder] = {}
+
+    def submit(self, n: int, gens, max_layers: int = 256, max_frontier: Optional[int] = None) -> int:
+        h = _JobHolder(n, gens, max_layers, max_frontier, 0, None, 0)
+        t = ctypes.c_uint64(0)
+        _check(N.lib().cg_queue_submit(self._q, ctypes.byref(h.job), ctypes.byref(h.res), ctypes.byref(t)))
+        self._jobs[int(t.value)] = h
+        return int(t.value)
+
+    def poll(self, ticket: int) -> int:
+        return N.lib().cg_queue_poll(self._q, ticket)
+
+    def wait(self, ticket: int, timeout_s: Optional[float] = None) -> GrowthResult:
+        us = -1 if timeout_s is None else int(timeout_s * 1e6)
+        rc = N.lib().cg_queue_wait(self._q, ticket, us)
+        if rc == N.CG_E_TIMEOUT:
+            raise TimeoutError(f"ticket {ticket} still running")
+        h = self._jobs.pop(ticket)
+        if rc < 0:
+            raise CGError(rc, N.lib().cg_last_error().decode())
+        return h.result()
+
+    def cancel(self, ticket: int) -> int:
+        return N.lib().cg_queue_cancel(self._q, ticket)
+
+    def close(self):
+        if self._q:
+            N.lib().cg_queue_destroy(self._q)
+            self._q = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,220 @@
+// The C ABI of libcayleygrowth.so (include/cayleygrowth.h and
+// include/cayleygrowth_testing.h). Every entry point catches everything:
+// no C++ exception crosses the boundary; failures become CG_E_* codes with
+// a thread-local detail string.
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/cayleygrowth.h"
+#include "../../include/cayleygrowth_testing.h"
+#include "engine.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const cg::Error &e) {
+        return fail(e.code, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(CG_E_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(CG_E_DEVICE, e.what());
+    } catch (...) {
+        return fail(CG_E_DEVICE, "unknown failure");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cg_strerror(int code) {
+    switch (code) {
+        case CG_OK: return "complete";
+        case CG_TRUNCATED: return "truncated by a stop rule";
+        case CG_PENDING: return "pending";
+        case CG_E_INVAL: return "invalid argument";
+        case CG_E_NOMEM: return "out of memory";
+        case CG_E_DEVICE: return "device error";
+        case CG_E_UNSUPPORTED: return "unsupported generating set";
+        case CG_E_BUSY: return "queue full";
+        case CG_E_CANCELLED: return "cancelled";
+        case CG_E_TIMEOUT: return "timed out";
+        default: return "unknown status";
+    }
+}
+
+const char *cg_last_error(void) { return g_last_error.c_str(); }
+
+int cg_growth_ex(const cg_job_t *job, cg_result_t *res, void *stream) {
+    return guarded([&]() -> int {
+        if (!job || !res || !res->layer_sizes) throw cg::Error(CG_E_INVAL, "NULL job or result");
+        const cg::JobSpec spec = cg::canonicalize(*job, false);
+        cg::Engine eng((hipStream_t)stream);
+        eng.run(spec, res);
+        return res->status;
+    });
+}
+
+int cg_growth(int n, const uint8_t *gens, int n_gens, int max_layers, uint64_t *out_layer_sizes) {
+    if (!out_layer_sizes) return fail(CG_E_INVAL, "NULL out_layer_sizes");
+    cg_job_t job{};
+    job.n = n;
+    job.gens = gens;
+    job.n_gens = n_gens;
+    job.max_layers = max_layers;
+    cg_result_t res{};
+    res.layer_sizes = out_layer_sizes;
+    return cg_growth_ex(&job, &res, nullptr);
+}
+
+// ---- kernel-level test entry points -------------------------------------------
+
+int cg_test_pack(int n, const uint8_t *h_states, uint64_t count, uint64_t *d_keys, void *stream) {
+    return guarded([&]() -> int {
+        if (n < 1 || n > 16 || (!h_states && count) || (!d_keys && count))
+            throw cg::Error(CG_E_INVAL, "bad pack arguments");
+        if (!count) return CG_OK;
+        hipStream_t s = (hipStream_t)stream;
+        cg::DevBuf rows;
+        rows.ensure(count * n);
+        CG_HIP(hipMemcpyAsync(rows.p, h_states, count * n, hipMemcpyHostToDevice, s));
+        cg::launch_pack(n, rows.as<uint8_t>(), count, d_keys, s);
+        CG_HIP(hipStreamSynchronize(s));
+        return CG_OK;
+    });
+}
+
+int cg_test_unpack(int n, const uint64_t *d_keys, uint64_t count, uint8_t *h_states, void *stream) {
+    return guarded([&]() -> int {
+        if (n < 1 || n > 16 || (!h_states && count) || (!d_keys && count))
+            throw cg::Error(CG_E_INVAL, "bad unpack arguments");
+        if (!count) return CG_OK;
+        hipStream_t s = (hipStream_t)stream;
+        cg::DevBuf rows;
+        rows.ensure(count * n);
+        cg::launch_unpack(n, d_keys, count, rows.as<uint8_t>(), s);
+        CG_HIP(hipMemcpyAsync(h_states, rows.p, count * n, hipMemcpyDeviceToHost, s));
+        CG_HIP(hipStreamSynchronize(s));
+        return CG_OK;
+    });
+}
+
+static std::vector<cg::GenSel> make_sels(int n, const uint8_t *h_gens, int k) {
+    if (n < 1 || n > 16 || k < 1 || !h_gens) throw cg::Error(CG_E_INVAL, "bad generator arguments");
+    std::vector<cg::GenSel> v(k);
+    for (int g = 0; g < k; ++g) {
+        bool seen[16] = {false};
+        for (int i = 0; i < n; ++i) {
+            const uint8_t x = h_gens[(size_t)g * n + i];
+            if (x >= n || seen[x]) throw cg::Error(CG_E_INVAL, "generator row is not a permutation");
+            seen[x] = true;
+        }
+        v[g] = cg::make_gensel(n, h_gens + (size_t)g * n);
+    }
+    return v;
+}
+
+int cg_test_expand(int n, const uint8_t *h_gens, int k, const uint64_t *d_frontier, uint64_t F,
+                   uint64_t *d_out, void *stream) {
+    return guarded([&]() -> int {
+        auto sels = make_sels(n, h_gens, k);
+        if (F && (!d_frontier || !d_out)) throw cg::Error(CG_E_INVAL, "NULL device pointer");
+        hipStream_t s = (hipStream_t)stream;
+        cg::PipeWork w;
+        w.init(s);
+        cg::DevBuf gs;
+        gs.ensure(sizeof(cg::GenSel) * k);
+        CG_HIP(hipMemcpyAsync(gs.p, sels.data(), sizeof(cg::GenSel) * k, hipMemcpyHostToDevice, s));
+        cg::launch_expand(d_frontier, F, gs.as<cg::GenSel>(), k, d_out, w);
+        CG_HIP(hipStreamSynchronize(s));
+        return CG_OK;
+    });
+}
+
+int cg_test_sort(uint64_t *d_keys, uint64_t *d_tmp, uint64_t count, int bit_lo, int bit_hi,
+                 void *stream) {
+    return guarded([&]() -> int {
+        if (bit_lo < 0 || bit_hi > 64 || bit_lo >= bit_hi) throw cg::Error(CG_E_INVAL, "bad bit range");
+        if (cg::sort_passes(bit_lo, bit_hi) > cg::kMaxPasses)
+            throw cg::Error(CG_E_INVAL, "bit range needs more than 8 passes");
+        if (count && (!d_keys || !d_tmp)) throw cg::Error(CG_E_INVAL, "NULL device pointer");
+        hipStream_t s = (hipStream_t)stream;
+        cg::PipeWork w;
+        w.init(s);
+        uint64_t *res = cg::radix_sort(d_keys, d_tmp, count, bit_lo, bit_hi, w);
+        if (res != d_keys)
+            CG_HIP(hipMemcpyAsync(d_keys, res, count * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+        uint32_t err = 0;
+        CG_HIP(hipMemcpyAsync(&err, w.err(), sizeof err, hipMemcpyDeviceToHost, s));
+        CG_HIP(hipStreamSynchronize(s));
+        if (err) throw cg::Error(CG_E_DEVICE, "kernel error flag set (look-back bound or offset check)");
+        return CG_OK;
+    });
+}
+
+int cg_test_dedup(const uint64_t *d_sorted, uint64_t C, const uint64_t *d_a, uint64_t na,
+                  const uint64_t *d_b, uint64_t nb, uint64_t *d_out, uint64_t *h_count,
+                  void *stream) {
+    return guarded([&]() -> int {
+        if (!h_count || (C && (!d_sorted || !d_out)) || (na && !d_a) || (nb && !d_b))
+            throw cg::Error(CG_E_INVAL, "NULL pointer");
+        hipStream_t s = (hipStream_t)stream;
+        cg::PipeWork w;
+        w.init(s);
+        cg::launch_dedup(d_sorted, C, d_a, na, d_b, nb, d_out, C, w.counter(), w);
+        uint64_t cnt = 0;
+        uint32_t err = 0;
+        CG_HIP(hipMemcpyAsync(&cnt, w.counter(), sizeof cnt, hipMemcpyDeviceToHost, s));
+        CG_HIP(hipMemcpyAsync(&err, w.err(), sizeof err, hipMemcpyDeviceToHost, s));
+        CG_HIP(hipStreamSynchronize(s));
+        if (err) throw cg::Error(CG_E_DEVICE, "kernel error flag set (look-back bound or offset check)");
+        *h_count = cnt;
+        return CG_OK;
+    });
+}
+
+int cg_test_layer_step(int n, const uint8_t *h_gens, int k, const uint64_t *d_frontier, uint64_t F,
+                       const uint64_t *d_prev, uint64_t np, uint64_t *d_out, uint64_t *h_count,
+                       void *stream) {
+    return guarded([&]() -> int {
+        auto sels = make_sels(n, h_gens, k);
+        if (!h_count || (F && (!d_frontier || !d_out)) || (np && !d_prev))
+            throw cg::Error(CG_E_INVAL, "NULL pointer");
+        hipStream_t s = (hipStream_t)stream;
+        cg::PipeWork w;
+        w.init(s);
+        cg::DevBuf gs, c0, c1;
+        gs.ensure(sizeof(cg::GenSel) * k);
+        CG_HIP(hipMemcpyAsync(gs.p, sels.data(), sizeof(cg::GenSel) * k, hipMemcpyHostToDevice, s));
+        const uint64_t C = F * (uint64_t)k;
+        c0.ensure(C * 8 + 8);
+        c1.ensure(C * 8 + 8);
+        const uint64_t *sorted =
+            cg::expand_sort(d_frontier, F, gs.as<cg::GenSel>(), k, c0.as<uint64_t>(), c1.as<uint64_t>(),
+                            4, 4 * n, w);
+        cg::launch_dedup(sorted, C, d_frontier, F, d_prev, np, d_out, C, w.counter(), w);
+        uint64_t cnt = 0;
+        uint32_t err = 0;
+        CG_HIP(hipMemcpyAsync(&cnt, w.counter(), sizeof cnt, hipMemcpyDeviceToHost, s));
+        CG_HIP(hipMemcpyAsync(&err, w.err(), sizeof err, hipMemcpyDeviceToHost, s));
+        CG_HIP(hipStreamSynchronize(s));
+        if (err) throw cg::Error(CG_E_DEVICE, "kernel error flag set (look-back bound or offset check)");
+        *h_count = cnt;
+        return CG_OK;
+    });
+}
+
+}  // extern "C"

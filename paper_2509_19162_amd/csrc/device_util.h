@@ -1,0 +1,165 @@
+// Device helpers for the gfx950 kernels: wave64 scans, decoupled look-back
+// words, wave-cooperative searches in sorted global arrays.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cg {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Number of set bits of `mask` below the calling lane (v_mbcnt pair).
+__device__ __forceinline__ uint32_t mask_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d) {
+    uint32_t lo = __shfl_up((uint32_t)v, d, kWave);
+    uint32_t hi = __shfl_up((uint32_t)(v >> 32), d, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+    uint32_t lo = __shfl((uint32_t)v, src, kWave);
+    uint32_t hi = __shfl((uint32_t)(v >> 32), src, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint64_t t = shfl_up64(v, d);
+        if (lane >= (uint32_t)d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan32(uint32_t v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, kWave);
+        if (lane >= (uint32_t)d) v += t;
+    }
+    return v;
+}
+
+// Exclusive prefix sum over the threads of a block of WAVES waves.
+// s_tmp must hold WAVES entries. Returns the calling thread's exclusive
+// prefix; *total receives the block total. Contains __syncthreads().
+template <int WAVES, class T>
+__device__ __forceinline__ T block_excl_scan(T v, T *s_tmp, T *total) {
+    const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x / kWave;
+    T incl;
+    if constexpr (sizeof(T) == 8)
+        incl = wave_incl_scan(v);
+    else
+        incl = wave_incl_scan32(v);
+    if (lane == kWave - 1) s_tmp[wave] = incl;
+    __syncthreads();
+    T off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        T x = s_tmp[w];
+        if ((uint32_t)w < wave) off += x;
+        tot += x;
+    }
+    *total = tot;
+    __syncthreads();
+    return off + incl - v;
+}
+
+// ---------------------------------------------------------------------------
+// Decoupled look-back words: [63:48] epoch, [47:46] flag, [45:0] value.
+// A word whose epoch differs from the launch's epoch reads as "not ready",
+// so the array needs no clearing between launches.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kFlagAggregate = 1;
+constexpr uint32_t kFlagInclusive = 2;
+constexpr uint64_t kValueMask = (1ull << 46) - 1;
+constexpr uint32_t kSpinLimit = 1u << 24;
+
+__device__ __forceinline__ uint64_t lb_word(uint32_t epoch, uint32_t flag, uint64_t v) {
+    return ((uint64_t)epoch << 48) | ((uint64_t)flag << 46) | (v & kValueMask);
+}
+
+__device__ __forceinline__ void lb_store(uint64_t *p, uint64_t w) {
+    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t lb_load(const uint64_t *p) {
+    return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of tile `tile` from the words of tiles tile-1, tile-2, ...
+// located at base[t * stride]. Tiles publish in ticket order, so every tile
+// waited on is already running; the wait is still bounded: on overrun the
+// error flag is raised and the (then meaningless) partial sum returned.
+__device__ __forceinline__ uint64_t lb_lookback(const uint64_t *base, uint64_t stride,
+                                                uint32_t tile, uint32_t epoch,
+                                                uint32_t *err) {
+    uint64_t excl = 0;
+    int64_t t = (int64_t)tile - 1;
+    uint32_t spins = 0;
+    while (t >= 0) {
+        uint64_t w = lb_load(base + (uint64_t)t * stride);
+        if ((uint32_t)(w >> 48) == epoch) {
+            excl += w & kValueMask;
+            if (((w >> 46) & 3u) == kFlagInclusive) break;
+            --t;
+        } else {
+            if (++spins > kSpinLimit) {
+                atomicOr(err, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    return excl;
+}
+
+// ---------------------------------------------------------------------------
+// Wave-cooperative search in a sorted global array: the first index i in
+// [0, n] with !(a[i] < key) (upper == false) or !(a[i] <= key) (upper ==
+// true). Every lane of the wave must call it with the same arguments; each
+// round probes 64 evenly spaced elements.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t wave_search(const uint64_t *a, uint64_t n, uint64_t key,
+                                                bool upper) {
+    const uint32_t lane = lane_id();
+    uint64_t lo = 0, hi = n;  // answer in [lo, hi]
+    while (hi - lo > kWave) {
+        const uint64_t step = (hi - lo + kWave - 1) / kWave;
+        const uint64_t p = lo + (uint64_t)lane * step;
+        bool pred = false;
+        if (p < hi) {
+            const uint64_t v = a[p];
+            pred = upper ? (v <= key) : (v < key);
+        }
+        const uint32_t c = (uint32_t)__popcll(__ballot(pred));
+        if (c == 0) return lo;
+        const uint64_t nlo = lo + (uint64_t)(c - 1) * step + 1;
+        const uint64_t cand = lo + (uint64_t)c * step;
+        const uint64_t nhi = (c < (uint32_t)kWave && cand < hi) ? cand : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    const uint64_t p = lo + lane;
+    bool pred = false;
+    if (p < hi) {
+        const uint64_t v = a[p];
+        pred = upper ? (v <= key) : (v < key);
+    }
+    return lo + (uint64_t)__popcll(__ballot(pred));
+}
+
+}  // namespace cg

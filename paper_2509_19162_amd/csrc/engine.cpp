@@ -1,0 +1,319 @@
+// Single-job growth: layer-by-layer breadth-first search from the start
+// vector (paper, section "Reminder on Cayley graphs, diameters, growth",
+// definition of Growth; the search itself is the breadth-first one named in
+// section "Examples and Tutorials").
+//
+// Per layer d, all on one stream:
+//   expand_sort   candidates s.g for every s in L_d and every generator g,
+//                 regenerated inside the first radix pass and sorted;
+//   dedup         keep the first key of each run that is in neither L_d nor
+//                 L_{d-1}, compacted in order into L_{d+1};
+//   read N        8 bytes back to the host (the only host-device sync).
+// The loop stops at an empty layer (complete), after max_layers layers, or
+// after recording the first layer larger than max_frontier (truncated).
+#include "engine.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+
+namespace cg {
+
+double now_seconds() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+JobSpec canonicalize(const cg_job_t &job, bool batch) {
+    JobSpec s;
+    if (job.n < 1 || job.n > 16) throw Error(CG_E_INVAL, "n must be in 1..16");
+    if (!job.gens || job.n_gens < 1) throw Error(CG_E_INVAL, "need at least one generator row");
+    if (job.max_layers < 1) throw Error(CG_E_INVAL, "max_layers must be >= 1");
+    const int n = job.n;
+    s.n = n;
+    s.max_layers = job.max_layers;
+    s.max_frontier = job.max_frontier;
+    s.flags = job.flags;
+    if (batch && (job.flags & (CG_ALLOW_DIRECTED | CG_KEEP_ALL_LAYERS)))
+        throw Error(CG_E_INVAL, "batched jobs cannot keep all layers or be directed");
+    if (batch && job.layers_out) throw Error(CG_E_INVAL, "batched jobs cannot export layers");
+    s.layers_out = job.layers_out;
+    s.layers_out_cap = job.layers_out ? job.layers_out_cap : 0;
+
+    std::vector<std::vector<uint8_t>> rows;
+    for (int g = 0; g < job.n_gens; ++g) {
+        const uint8_t *r = job.gens + (size_t)g * n;
+        bool seen[16] = {false};
+        bool ident = true;
+        for (int i = 0; i < n; ++i) {
+            if (r[i] >= n || seen[r[i]]) {
+                char buf[96];
+                std::snprintf(buf, sizeof buf, "generator row %d is not a permutation of 0..%d", g, n - 1);
+                throw Error(CG_E_INVAL, buf);
+            }
+            seen[r[i]] = true;
+            ident = ident && r[i] == i;
+        }
+        if (ident) continue;
+        std::vector<uint8_t> v(r, r + n);
+        if (std::find(rows.begin(), rows.end(), v) == rows.end()) rows.push_back(v);
+    }
+    s.k = (int)rows.size();
+    for (auto &r : rows) s.gens.insert(s.gens.end(), r.begin(), r.end());
+
+    // closed under inverses?
+    s.inverse_closed = true;
+    for (auto &r : rows) {
+        std::vector<uint8_t> inv(n);
+        for (int i = 0; i < n; ++i) inv[r[i]] = (uint8_t)i;
+        if (std::find(rows.begin(), rows.end(), inv) == rows.end()) {
+            s.inverse_closed = false;
+            break;
+        }
+    }
+    if (!s.inverse_closed && !(job.flags & CG_ALLOW_DIRECTED))
+        throw Error(CG_E_UNSUPPORTED,
+                    "generating set is not closed under inverses (pass CG_ALLOW_DIRECTED)");
+
+    if (job.flags & CG_START_STATE) {
+        if (!job.start) throw Error(CG_E_INVAL, "CG_START_STATE without a start vector");
+        for (int i = 0; i < n; ++i) {
+            if (job.start[i] > 15) throw Error(CG_E_INVAL, "start entries must be 0..15");
+            s.start[i] = job.start[i];
+        }
+    } else {
+        for (int i = 0; i < n; ++i) s.start[i] = (uint8_t)i;
+    }
+    // orbit size bound: multinomial n! / prod(mult!)
+    int mult[16] = {0};
+    for (int i = 0; i < n; ++i) mult[s.start[i]]++;
+    uint64_t b = 1;
+    int placed = 0;
+    for (int v = 0; v < 16; ++v) {
+        for (int j = 1; j <= mult[v]; ++j) {
+            ++placed;
+            b = b * (uint64_t)placed / (uint64_t)j;  // exact: running binomial products
+        }
+    }
+    s.orbit_bound = b;
+    return s;
+}
+
+Engine::Engine(hipStream_t user_stream) {
+    if (user_stream) {
+        stream_ = user_stream;
+    } else {
+        CG_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
+        own_stream_ = true;
+    }
+    w_.init(stream_);
+    prof_.stream = stream_;
+    CG_HIP(hipHostMalloc((void **)&host_small_, 64, hipHostMallocDefault));
+}
+
+Engine::~Engine() {
+    if (host_small_) (void)hipHostFree(host_small_);
+    if (own_stream_) {
+        (void)hipStreamSynchronize(stream_);
+        (void)hipStreamDestroy(stream_);
+    }
+}
+
+uint64_t Engine::read_counter() {
+    CG_HIP(hipMemcpyAsync(host_small_, w_.counter(), sizeof(uint64_t), hipMemcpyDeviceToHost, stream_));
+    CG_HIP(hipMemcpyAsync(host_small_ + 1, w_.err(), sizeof(uint32_t), hipMemcpyDeviceToHost, stream_));
+    CG_HIP(hipStreamSynchronize(stream_));
+    if (((uint32_t *)(host_small_ + 1))[0] != 0)
+        throw Error(CG_E_DEVICE, "kernel error flag set (look-back bound or offset check)");
+    return host_small_[0];
+}
+
+void Engine::export_layer(const JobSpec &spec, const uint64_t *d_keys, uint64_t count,
+                          uint64_t &written) {
+    if (!spec.layers_out || written >= spec.layers_out_cap) {
+        written += count;
+        return;
+    }
+    const uint64_t take = std::min(count, spec.layers_out_cap - written);
+    stage_.ensure(take * (uint64_t)spec.n + 64, 1.25);
+    launch_unpack(spec.n, d_keys, take, stage_.as<uint8_t>(), stream_);
+    CG_HIP(hipMemcpyAsync(spec.layers_out + written * spec.n, stage_.p, take * spec.n,
+                          hipMemcpyDeviceToHost, stream_));
+    CG_HIP(hipStreamSynchronize(stream_));
+    written += count;
+}
+
+void fill_kstats(const Profiler &p, cg_result_t *res) {
+    res->n_kstats = 0;
+    if (!p.on) return;
+    for (int k = 0; k < K_NUM && res->n_kstats < CG_KSTAT_MAX; ++k) {
+        if (!p.launches[k]) continue;
+        cg_kstat_t &s = res->kstats[res->n_kstats++];
+        std::memset(&s, 0, sizeof s);
+        std::snprintf(s.name, sizeof s.name, "%s", kernel_kind_name(k));
+        s.launches = p.launches[k];
+        s.total_ms = p.total_ms[k];
+        s.alg_bytes = p.bytes[k];
+        s.items = p.items[k];
+    }
+}
+
+void Engine::run(const JobSpec &spec, cg_result_t *res) {
+    const double t0 = now_seconds();
+    uint64_t *sizes = res->layer_sizes;
+    std::memset(sizes, 0, sizeof(uint64_t) * (size_t)spec.max_layers);
+    res->status = CG_OK;
+    res->num_layers = 1;
+    res->states_expanded = 0;
+    res->candidates = 0;
+    res->device_ms = 0;
+    res->n_kstats = 0;
+    sizes[0] = 1;
+
+    prof_.on = (spec.flags & CG_PROFILE) != 0;
+    for (int i = 0; i < K_NUM; ++i) {
+        prof_.total_ms[i] = prof_.bytes[i] = prof_.items[i] = 0;
+        prof_.launches[i] = 0;
+    }
+    w_.prof = prof_.on ? &prof_ : nullptr;
+
+    const int n = spec.n, k = spec.k;
+    const bool keep_all = (spec.flags & CG_KEEP_ALL_LAYERS) != 0;
+    const bool directed = !spec.inverse_closed;
+    if (directed) throw Error(CG_E_UNSUPPORTED, "directed growth is not available in this build");
+
+    hipEvent_t ev0, ev1;
+    CG_HIP(hipEventCreate(&ev0));
+    CG_HIP(hipEventCreate(&ev1));
+    CG_HIP(hipEventRecord(ev0, stream_));
+
+    uint64_t written = 0;
+    const uint64_t key0 = pack_host(n, spec.start);
+
+    // generator selectors
+    std::vector<GenSel> hsel(k > 0 ? k : 1);
+    for (int g = 0; g < k; ++g) hsel[g] = make_gensel(n, spec.gens.data() + (size_t)g * n);
+    gsel_.ensure(sizeof(GenSel) * hsel.size());
+    CG_HIP(hipMemcpyAsync(gsel_.p, hsel.data(), sizeof(GenSel) * hsel.size(), hipMemcpyHostToDevice,
+                          stream_));
+
+    // layer storage
+    std::vector<uint64_t> off;  // keep_all: offsets of the layers in the arena
+    uint64_t total = 1;         // states recorded so far
+    if (keep_all) {
+        // the whole orbit when it fits comfortably, else grow on demand
+        size_t free_b = 0, total_b = 0;
+        CG_HIP(hipMemGetInfo(&free_b, &total_b));
+        uint64_t first = std::min<uint64_t>(spec.orbit_bound, 1ull << 20);
+        if (spec.orbit_bound <= (uint64_t)(free_b / 4 / sizeof(uint64_t))) first = spec.orbit_bound;
+        arena_.ensure(first * sizeof(uint64_t));
+        CG_HIP(hipMemcpyAsync(arena_.p, &key0, 8, hipMemcpyHostToDevice, stream_));
+        off.push_back(0);
+        off.push_back(1);
+    } else {
+        lay_[0].ensure(64);  // L_{d-1} (empty at d = 0)
+        lay_[1].ensure(64);
+        CG_HIP(hipMemcpyAsync(lay_[1].p, &key0, 8, hipMemcpyHostToDevice, stream_));
+    }
+    int ip = 0, ic = 1, in = 2;  // indices of L_{d-1}, L_d, L_{d+1} in lay_
+    uint64_t np = 0, F = 1;
+    export_layer(spec, keep_all ? arena_.as<uint64_t>() : lay_[1].as<uint64_t>(), 1, written);
+
+    const int bit_lo = 4, bit_hi = 4 * n;
+    int layers = 1;
+    int status = CG_OK;
+    for (;;) {
+        if (k == 0) {
+            status = CG_OK;
+            break;
+        }
+        if (spec.max_frontier && F > spec.max_frontier) {
+            status = CG_TRUNCATED;
+            break;
+        }
+        if (layers >= spec.max_layers) {
+            status = CG_TRUNCATED;
+            break;
+        }
+        const uint64_t C = F * (uint64_t)k;
+        const uint64_t room = spec.orbit_bound > total ? spec.orbit_bound - total : 0;
+        const uint64_t out_cap = std::max<uint64_t>(1, std::min(C, room));
+        cand0_.ensure(C * sizeof(uint64_t), 1.25);
+        cand1_.ensure(C * sizeof(uint64_t), 1.25);
+
+        const uint64_t *Ld, *Lp;
+        uint64_t *out;
+        if (keep_all) {
+            const uint64_t need = (total + out_cap) * sizeof(uint64_t);
+            if (need > arena_.bytes) {
+                // grow, keeping every layer (the arena holds them all)
+                size_t want = std::max<size_t>(need, (size_t)(arena_.bytes * 1.5));
+                want = std::min<size_t>(want, std::max<size_t>(need, spec.orbit_bound * 8));
+                DevBuf bigger;
+                bigger.ensure(want);
+                CG_HIP(hipMemcpyAsync(bigger.p, arena_.p, total * sizeof(uint64_t),
+                                      hipMemcpyDeviceToDevice, stream_));
+                CG_HIP(hipStreamSynchronize(stream_));
+                std::swap(arena_.p, bigger.p);
+                std::swap(arena_.bytes, bigger.bytes);
+            }
+            const uint64_t d = off.size() - 2;  // index of L_d
+            Ld = arena_.as<uint64_t>() + off[d];
+            Lp = d > 0 ? arena_.as<uint64_t>() + off[d - 1] : nullptr;
+            out = arena_.as<uint64_t>() + total;
+        } else {
+            lay_[in].ensure(out_cap * sizeof(uint64_t), 1.25);
+            Ld = lay_[ic].as<uint64_t>();
+            Lp = lay_[ip].as<uint64_t>();
+            out = lay_[in].as<uint64_t>();
+        }
+
+        const uint64_t *sorted = expand_sort(Ld, F, gsel_.as<GenSel>(), k, cand0_.as<uint64_t>(),
+                                             cand1_.as<uint64_t>(), bit_lo, bit_hi, w_);
+        launch_dedup(sorted, C, Ld, F, Lp, np, out, out_cap, w_.counter(), w_);
+        const uint64_t N = read_counter();
+        if (N > C || N > room) throw Error(CG_E_DEVICE, "layer size out of range (device error)");
+        if (prof_.on) {
+            prof_.collect();
+            prof_.bytes[K_DEDUP] += 8.0 * (double)N;
+        }
+        res->states_expanded += F;
+        res->candidates += C;
+        if (N == 0) {
+            status = CG_OK;
+            break;
+        }
+        sizes[layers++] = N;
+        export_layer(spec, out, N, written);
+        total += N;
+        if (keep_all) {
+            off.push_back(total);
+        } else {
+            const int t = ip;
+            ip = ic;
+            ic = in;
+            in = t;
+        }
+        np = F;
+        F = N;
+    }
+
+    CG_HIP(hipEventRecord(ev1, stream_));
+    CG_HIP(hipEventSynchronize(ev1));
+    float ms = 0;
+    CG_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    prof_.collect();
+    fill_kstats(prof_, res);
+    res->device_ms = ms;
+    res->status = status;
+    res->num_layers = layers;
+    const double t1 = now_seconds();
+    res->t_submit = t0;
+    res->t_admit = t0;
+    res->t_done = t1;
+}
+
+}  // namespace cg

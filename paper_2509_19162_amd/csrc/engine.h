@@ -1,0 +1,61 @@
+// Single-job growth engine: the layer loop of the breadth-first search.
+#pragma once
+
+#include <vector>
+
+#include "../../include/cayleygrowth.h"
+#include "internal.h"
+
+namespace cg {
+
+// A validated job (generators deduplicated, identity dropped).
+struct JobSpec {
+    int n = 0;
+    int k = 0;                  // distinct non-identity generators
+    std::vector<uint8_t> gens;  // k rows of n bytes
+    bool inverse_closed = true;
+    uint8_t start[16] = {0};
+    int max_layers = 1;
+    uint64_t max_frontier = 0;
+    uint32_t flags = 0;
+    uint8_t *layers_out = nullptr;
+    uint64_t layers_out_cap = 0;
+    uint64_t orbit_bound = 1;  // n! / prod(mult!) of the start's entries
+};
+
+// Validates and canonicalises a job; throws Error(CG_E_INVAL / _UNSUPPORTED).
+JobSpec canonicalize(const cg_job_t &job, bool batch);
+
+double now_seconds();
+
+class Engine {
+public:
+    explicit Engine(hipStream_t user_stream);
+    ~Engine();
+    Engine(const Engine &) = delete;
+    Engine &operator=(const Engine &) = delete;
+
+    // Runs the job to completion; fills res (layer_sizes must hold
+    // spec.max_layers entries). Throws Error on failure.
+    void run(const JobSpec &spec, cg_result_t *res);
+
+    PipeWork &work() { return w_; }
+    hipStream_t stream() const { return stream_; }
+    // Reads back one u64 counter and the kernel error flag (synchronises).
+    uint64_t read_counter();
+
+private:
+    void export_layer(const JobSpec &spec, const uint64_t *d_keys, uint64_t count,
+                      uint64_t &written);
+
+    hipStream_t stream_ = nullptr;
+    bool own_stream_ = false;
+    PipeWork w_;
+    Profiler prof_;
+    DevBuf gsel_, cand0_, cand1_, lay_[3], arena_, stage_;
+    uint64_t *host_small_ = nullptr;  // pinned: counter + error flag
+};
+
+void fill_kstats(const Profiler &p, cg_result_t *res);
+
+}  // namespace cg

@@ -1,0 +1,158 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libcayleygrowth.so. Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace cg {
+
+// ---------------------------------------------------------------------------
+// Errors: host code throws cg::Error; the C ABI turns it into a status code.
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char *what, const char *file, int line);
+#define CG_HIP(x) ::cg::hip_check((x), #x, __FILE__, __LINE__)
+
+// ---------------------------------------------------------------------------
+// State keys. A state s (n <= 16 entries, each 0..15) is the uint64
+//   key(s) = sum_i s[i] << 4*(n-1-i)
+// so numeric order is lexicographic order. For every state of one orbit the
+// last entry s[n-1] (nibble 0) follows from the others (the multiset of
+// entries is fixed), so sorting and comparing on bits [4, 4n) is exact.
+// Batched jobs put the job index above bit 4*16 - the tag bits - see batch.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kSentinel = ~0ull;  // never a key: nibbles 15 everywhere
+
+uint64_t pack_host(int n, const uint8_t *s);
+void unpack_host(int n, uint64_t key, uint8_t *s);
+
+// Byte-permute selectors of one generator (see make_gensel in expand.hip).
+struct GenSel {
+    uint32_t sel[8];
+};
+GenSel make_gensel(int n, const uint8_t *g);
+
+// ---------------------------------------------------------------------------
+// Per-kernel HIP-event profiling (CG_PROFILE).
+// ---------------------------------------------------------------------------
+enum KernelKind {
+    K_EXPAND = 0,     // stand-alone permute-expand
+    K_HIST = 1,       // one-read digit histograms of every sort pass
+    K_SCAN = 2,       // digit offsets
+    K_SORT_FUSED = 3, // first sort pass, candidates regenerated from frontier
+    K_SORT = 4,       // later sort passes
+    K_DEDUP = 5,      // unique + set difference + compaction
+    K_AUX = 6,        // small bookkeeping kernels
+    K_NUM = 7
+};
+const char *kernel_kind_name(int k);
+
+struct Profiler {
+    bool on = false;
+    hipStream_t stream = nullptr;
+    struct Pending {
+        int kind;
+        hipEvent_t a, b;
+        double bytes, items;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    double total_ms[K_NUM] = {0};
+    double bytes[K_NUM] = {0};
+    double items[K_NUM] = {0};
+    uint64_t launches[K_NUM] = {0};
+
+    hipEvent_t get_event();
+    // Record the start event of a launch of `kind` (no-op when off).
+    void begin(int kind);
+    // Record the end event; alg_bytes/items are this launch's algorithmic
+    // traffic and processed keys.
+    void end(int kind, double alg_bytes, double items);
+    // After a stream synchronisation: fold finished launches into totals.
+    void collect();
+    ~Profiler();
+};
+
+// ---------------------------------------------------------------------------
+// Device scratch of the layer pipeline (owned by an Engine, grown on demand).
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    // Grow to at least `need` bytes (contents are not kept). Returns true if
+    // the buffer was reallocated.
+    bool ensure(size_t need, double slack = 1.0);
+    void release();
+    ~DevBuf() { release(); }
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+struct PipeWork {
+    DevBuf hist;     // uint64 [kMaxPasses][256]: digit counts of every pass
+    DevBuf base;     // uint64 [kMaxPasses][256]: exclusive digit offsets
+    DevBuf small;    // uint32 tickets[32], err flag, uint64 counters
+    DevBuf status;   // uint64 look-back words: tiles x 256 (sort), tiles (dedup)
+    uint32_t epoch = 0;  // 16-bit epoch of the look-back words
+    hipStream_t stream = nullptr;
+    Profiler *prof = nullptr;
+
+    uint32_t *tickets() const { return small.as<uint32_t>(); }          // 32
+    uint32_t *err() const { return small.as<uint32_t>() + 32; }        // 1
+    uint64_t *counter() const { return small.as<uint64_t>() + 32; }    // 8 x u64
+    void init(hipStream_t s);
+    // Make room for `words` look-back words (new memory is cleared).
+    void ensure_status(uint64_t words);
+    // Epoch of the next look-back launch; on wrap-around the words are
+    // cleared so that no stale word can carry a live epoch.
+    uint32_t next_epoch();
+};
+
+constexpr int kMaxPasses = 8;
+
+// ---- util.hip ---------------------------------------------------------------
+// Zero a[0..na) (uint32) and b[0..nb) (uint64) with one small kernel.
+void launch_clear(uint32_t *a, uint32_t na, uint64_t *b, uint32_t nb, hipStream_t s);
+
+// ---- expand.hip -------------------------------------------------------------
+void launch_expand(const uint64_t *frontier, uint64_t F, const GenSel *d_gsel,
+                   int k, uint64_t *out, PipeWork &w);
+void launch_pack(int n, const uint8_t *d_rows, uint64_t count, uint64_t *d_keys,
+                 hipStream_t s);
+void launch_unpack(int n, const uint64_t *d_keys, uint64_t count,
+                   uint8_t *d_rows, hipStream_t s);
+
+// ---- radix_sort.hip ----------------------------------------------------------
+int sort_passes(int bit_lo, int bit_hi);
+// Sorts keys[0..count) on bits [bit_lo, bit_hi); returns the buffer that
+// holds the result (keys or tmp).
+uint64_t *radix_sort(uint64_t *keys, uint64_t *tmp, uint64_t count, int bit_lo,
+                     int bit_hi, PipeWork &w);
+// Expands frontier[0..F) by the k generators and sorts the k*F candidates on
+// bits [bit_lo, bit_hi); the first pass regenerates candidates from the
+// frontier instead of reading them. Returns buf0 or buf1 (each k*F keys).
+uint64_t *expand_sort(const uint64_t *frontier, uint64_t F, const GenSel *d_gsel,
+                      int k, uint64_t *buf0, uint64_t *buf1, int bit_lo,
+                      int bit_hi, PipeWork &w);
+uint64_t sort_status_words(uint64_t count);
+uint64_t expand_sort_status_words(uint64_t F, int k);
+
+// ---- dedup.hip ----------------------------------------------------------------
+// Unique + set difference against sorted a[0..na) and b[0..nb) + compaction
+// into out (room for out_cap keys; survivors beyond it are not written and
+// raise the error flag); the number of kept keys lands in *d_count.
+void launch_dedup(const uint64_t *sorted, uint64_t C, const uint64_t *a,
+                  uint64_t na, const uint64_t *b, uint64_t nb, uint64_t *out,
+                  uint64_t out_cap, uint64_t *d_count, PipeWork &w);
+uint64_t dedup_status_words(uint64_t C);
+
+}  // namespace cg

@@ -1,0 +1,340 @@
+// Stable LSD radix sort of 64-bit state keys on a bit range, for gfx950.
+//
+// The growth step needs the candidates of a layer in sorted order so that
+// repeats become neighbours and the set difference against the two previous
+// (sorted) layers becomes a merge. The paper says only that its BFS is
+// efficient and not straightforward (section "Examples and Tutorials"); the
+// sort-based design here is this library's own.
+//
+// Structure (one-sweep LSD):
+//   1. hist    one read of the keys computes the 8-bit digit histograms of
+//              every pass at once (LDS counters, one flush per block);
+//   2. scan    exclusive prefix of each pass's 256 digit counts;
+//   3. pass p  each 4096-key tile ranks its keys per digit with wave64
+//              ballots (8 ballots build the mask of lanes sharing a digit,
+//              v_mbcnt gives the rank below), publishes its per-digit counts
+//              as decoupled look-back words, reads the exclusive prefix of
+//              the tiles before it, reorders the tile in LDS by digit and
+//              writes runs of equal digits to consecutive addresses.
+// Each pass reads and writes every key once (16 bytes per key).
+//
+// The first pass of expand_sort() regenerates the candidates from the
+// frontier (permute-expand fused into the pass), so the unsorted candidate
+// array is never written.
+#include "internal.h"
+#include "device_util.h"
+#include "expand_device.h"
+
+namespace cg {
+
+namespace {
+
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / kWave;
+constexpr int kIpt = 16;
+constexpr int kTile = kBlock * kIpt;  // 4096 keys
+constexpr int kWaveSeg = kWave * kIpt;  // keys owned by one wave
+
+static_assert(kBlock == kRadix, "one thread per digit in the look-back");
+
+// ---- key sources --------------------------------------------------------------
+// A source maps (tile, index in tile) to a key and knows each tile's length.
+
+struct ArraySrc {
+    const uint64_t *keys;
+    uint64_t count;
+    struct Tile {
+        const uint64_t *p;
+        uint32_t n;
+        __device__ __forceinline__ uint64_t get(uint32_t i) const { return p[i]; }
+    };
+    __device__ __forceinline__ Tile tile(uint32_t t) const {
+        const uint64_t start = (uint64_t)t * kTile;
+        const uint64_t left = count - start;
+        return Tile{keys + start, (uint32_t)(left < (uint64_t)kTile ? left : (uint64_t)kTile)};
+    }
+    __host__ __device__ uint32_t tiles() const { return (uint32_t)((count + kTile - 1) / kTile); }
+};
+
+// Tile t covers frontier block t / k under generator t % k: consecutive
+// tiles share a frontier block, so its reads after the first hit the caches.
+struct ExpandSrc {
+    const uint64_t *frontier;
+    uint64_t F;
+    const GenSel *gsel;
+    uint32_t k;
+    struct Tile {
+        const uint64_t *p;
+        GenSel sel;
+        uint32_t n;
+        __device__ __forceinline__ uint64_t get(uint32_t i) const { return apply_gensel(p[i], sel); }
+    };
+    __device__ __forceinline__ Tile tile(uint32_t t) const {
+        const uint32_t b = t / k;
+        const uint32_t g = t - b * k;
+        const uint64_t start = (uint64_t)b * kTile;
+        const uint64_t left = F - start;
+        return Tile{frontier + start, gsel[g],
+                    (uint32_t)(left < (uint64_t)kTile ? left : (uint64_t)kTile)};
+    }
+    __host__ __device__ uint32_t tiles() const {
+        return (uint32_t)(((F + kTile - 1) / kTile) * (uint64_t)k);
+    }
+};
+
+struct PassDesc {
+    int shift[kMaxPasses];
+    uint32_t mask[kMaxPasses];
+    int passes;
+};
+
+// ---- 1. histograms of all passes -------------------------------------------------
+template <class Src>
+__global__ __launch_bounds__(kBlock) void hist_kernel(Src src, uint32_t ntiles, PassDesc pd,
+                                                      unsigned long long *__restrict__ ghist) {
+    __shared__ uint32_t s_h[kMaxPasses][kRadix];
+    for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kBlock) (&s_h[0][0])[i] = 0;
+    __syncthreads();
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const auto T = src.tile(t);
+        for (uint32_t i = threadIdx.x; i < T.n; i += kBlock) {
+            const uint64_t key = T.get(i);
+            for (int p = 0; p < pd.passes; ++p)
+                atomicAdd(&s_h[p][(uint32_t)(key >> pd.shift[p]) & pd.mask[p]], 1u);
+        }
+    }
+    __syncthreads();
+    for (int p = 0; p < pd.passes; ++p) {
+        const uint32_t c = s_h[p][threadIdx.x];
+        if (c) atomicAdd(&ghist[p * kRadix + threadIdx.x], (unsigned long long)c);
+    }
+}
+
+// ---- 2. digit offsets ---------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void digit_scan_kernel(const unsigned long long *__restrict__ ghist,
+                                                            unsigned long long *__restrict__ gbase) {
+    __shared__ unsigned long long s_tmp[kWaves];
+    const int p = blockIdx.x;
+    const unsigned long long v = ghist[p * kRadix + threadIdx.x];
+    unsigned long long tot;
+    const unsigned long long ex = block_excl_scan<kWaves>(v, s_tmp, &tot);
+    gbase[p * kRadix + threadIdx.x] = ex;
+}
+
+__global__ void clear_kernel(unsigned long long *__restrict__ a, uint32_t na,
+                             uint32_t *__restrict__ b, uint32_t nb) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < na) a[i] = 0;
+    if (i < nb) b[i] = 0;
+}
+
+// ---- 3. one scatter pass -----------------------------------------------------------------
+template <class Src>
+__global__ __launch_bounds__(kBlock) void onesweep_kernel(
+    Src src, uint64_t *__restrict__ out, uint64_t total, int shift, uint32_t dmask,
+    const unsigned long long *__restrict__ digit_base, uint64_t *__restrict__ status,
+    uint32_t *__restrict__ ticket, uint32_t epoch, uint32_t *__restrict__ err) {
+    __shared__ uint64_t s_keys[kTile];
+    __shared__ uint32_t s_cnt[kWaves][kRadix];
+    __shared__ uint64_t s_gstart[kRadix];
+    __shared__ uint32_t s_lstart[kRadix];
+    __shared__ uint32_t s_scan[kWaves];
+    __shared__ uint32_t s_tile;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (kWave - 1);
+    const uint32_t wave = tid / kWave;
+
+    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const auto T = src.tile(tile);
+    const uint32_t nvalid = T.n;
+
+    // Wave w owns keys [w*1024, (w+1)*1024) of the tile; item j of lane l is
+    // key w*1024 + j*64 + l, so (wave, item, lane) order is index order and
+    // the per-wave running counts give a stable rank.
+    uint64_t key[kIpt];
+#pragma unroll
+    for (int j = 0; j < kIpt; ++j) {
+        const uint32_t i = wave * kWaveSeg + j * kWave + lane;
+        key[j] = i < nvalid ? T.get(i) : kSentinel;
+    }
+    uint32_t rank[kIpt];
+#pragma unroll
+    for (int j = 0; j < kIpt; ++j) {
+        const uint32_t i = wave * kWaveSeg + j * kWave + lane;
+        const bool valid = i < nvalid;
+        const uint32_t d = (uint32_t)(key[j] >> shift) & dmask;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t below = mask_rank(peers);
+        const uint32_t cnt = (uint32_t)__popcll(peers);
+        uint32_t old = 0;
+        if (valid) old = s_cnt[wave][d];
+        if (valid && below == 0) s_cnt[wave][d] = old + cnt;
+        rank[j] = old + below;
+    }
+    __syncthreads();
+
+    // thread tid owns digit tid: wave prefix, tile count, look-back
+    {
+        const uint32_t d = tid;
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t c = s_cnt[w][d];
+            s_cnt[w][d] = run;
+            run += c;
+        }
+        uint64_t *my = status + (uint64_t)tile * kRadix + d;
+        uint64_t excl = 0;
+        if (tile == 0) {
+            lb_store(my, lb_word(epoch, kFlagInclusive, run));
+        } else {
+            lb_store(my, lb_word(epoch, kFlagAggregate, run));
+            excl = lb_lookback(status + d, kRadix, tile, epoch, err);
+            lb_store(my, lb_word(epoch, kFlagInclusive, excl + run));
+        }
+        s_gstart[d] = (uint64_t)digit_base[d] + excl;
+        uint32_t tot;
+        s_lstart[d] = block_excl_scan<kWaves>(run, s_scan, &tot);
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int j = 0; j < kIpt; ++j) {
+        const uint32_t i = wave * kWaveSeg + j * kWave + lane;
+        if (i < nvalid) {
+            const uint32_t d = (uint32_t)(key[j] >> shift) & dmask;
+            s_keys[s_lstart[d] + s_cnt[wave][d] + rank[j]] = key[j];
+        }
+    }
+    __syncthreads();
+
+    for (uint32_t i = tid; i < nvalid; i += kBlock) {
+        const uint64_t k = s_keys[i];
+        const uint32_t d = (uint32_t)(k >> shift) & dmask;
+        const uint64_t gpos = s_gstart[d] + (i - s_lstart[d]);
+        if (gpos < total)
+            out[gpos] = k;
+        else
+            atomicOr(err, 2u);  // inconsistent offsets: never write out of bounds
+    }
+}
+
+PassDesc make_passes(int bit_lo, int bit_hi) {
+    PassDesc pd{};
+    pd.passes = 0;
+    for (int s = bit_lo; s < bit_hi; s += kRadixBits) {
+        const int bits = (bit_hi - s) < kRadixBits ? (bit_hi - s) : kRadixBits;
+        pd.shift[pd.passes] = s;
+        pd.mask[pd.passes] = (1u << bits) - 1u;
+        ++pd.passes;
+    }
+    return pd;
+}
+
+uint32_t hist_grid(uint32_t ntiles) {
+    const uint32_t cap = 2048;
+    return ntiles < cap ? (ntiles ? ntiles : 1) : cap;
+}
+
+template <class Src>
+uint64_t *run_sort(const Src &first_src, uint64_t count, uint64_t *buf0, uint64_t *buf1,
+                   int bit_lo, int bit_hi, PipeWork &w, bool fused_first,
+                   double first_read_bytes) {
+    const PassDesc pd = make_passes(bit_lo, bit_hi);
+    if (pd.passes > kMaxPasses) throw Error(-1, "sort bit range needs more than 8 passes");
+    unsigned long long *hist = w.hist.as<unsigned long long>();
+    unsigned long long *base = w.base.as<unsigned long long>();
+
+    if (w.prof) w.prof->begin(K_AUX);
+    hipLaunchKernelGGL(clear_kernel, dim3(8), dim3(256), 0, w.stream, hist,
+                       (uint32_t)(kMaxPasses * kRadix), w.tickets(), 32u);
+    CG_HIP(hipGetLastError());
+    if (w.prof) w.prof->end(K_AUX, 0, 0);
+
+    const uint32_t t0 = first_src.tiles();
+    if (w.prof) w.prof->begin(K_HIST);
+    hipLaunchKernelGGL(hist_kernel<Src>, dim3(hist_grid(t0)), dim3(kBlock), 0, w.stream, first_src,
+                       t0, pd, hist);
+    CG_HIP(hipGetLastError());
+    if (w.prof) w.prof->end(K_HIST, first_read_bytes, (double)count);
+
+    if (w.prof) w.prof->begin(K_SCAN);
+    hipLaunchKernelGGL(digit_scan_kernel, dim3(pd.passes), dim3(kBlock), 0, w.stream, hist, base);
+    CG_HIP(hipGetLastError());
+    if (w.prof) w.prof->end(K_SCAN, 0, 0);
+
+    uint64_t *cur_out = buf0;
+    const uint64_t *cur_in = nullptr;
+    for (int p = 0; p < pd.passes; ++p) {
+        if (p == 0) {
+            const uint32_t epoch = w.next_epoch();
+            const int kind = fused_first ? K_SORT_FUSED : K_SORT;
+            if (w.prof) w.prof->begin(kind);
+            hipLaunchKernelGGL(onesweep_kernel<Src>, dim3(t0), dim3(kBlock), 0, w.stream, first_src,
+                               cur_out, count, pd.shift[p], pd.mask[p], base + p * kRadix,
+                               w.status.as<uint64_t>(), w.tickets() + p, epoch, w.err());
+            CG_HIP(hipGetLastError());
+            if (w.prof) w.prof->end(kind, first_read_bytes + 8.0 * (double)count, (double)count);
+        } else {
+            const uint32_t epoch = w.next_epoch();
+            const ArraySrc s{cur_in, count};
+            if (w.prof) w.prof->begin(K_SORT);
+            hipLaunchKernelGGL(onesweep_kernel<ArraySrc>, dim3(s.tiles()), dim3(kBlock), 0, w.stream,
+                               s, cur_out, count, pd.shift[p], pd.mask[p], base + p * kRadix,
+                               w.status.as<uint64_t>(), w.tickets() + p, epoch, w.err());
+            CG_HIP(hipGetLastError());
+            if (w.prof) w.prof->end(K_SORT, 16.0 * (double)count, (double)count);
+        }
+        cur_in = cur_out;
+        cur_out = (cur_out == buf0) ? buf1 : buf0;
+    }
+    return const_cast<uint64_t *>(cur_in);
+}
+
+}  // namespace
+
+int sort_passes(int bit_lo, int bit_hi) { return make_passes(bit_lo, bit_hi).passes; }
+
+uint64_t sort_status_words(uint64_t count) { return ((count + kTile - 1) / kTile) * kRadix; }
+
+uint64_t expand_sort_status_words(uint64_t F, int k) {
+    const uint64_t a = ((F + kTile - 1) / kTile) * (uint64_t)k * kRadix;
+    const uint64_t b = sort_status_words(F * (uint64_t)k);
+    return a > b ? a : b;
+}
+
+uint64_t *radix_sort(uint64_t *keys, uint64_t *tmp, uint64_t count, int bit_lo, int bit_hi,
+                     PipeWork &w) {
+    if (count <= 1 || bit_lo >= bit_hi) return keys;
+    w.ensure_status(sort_status_words(count));
+    const ArraySrc src{keys, count};
+    // pass 0 reads `keys` and writes `tmp`; then they alternate
+    return run_sort(src, count, tmp, keys, bit_lo, bit_hi, w, false, 8.0 * (double)count);
+}
+
+uint64_t *expand_sort(const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,
+                      uint64_t *buf0, uint64_t *buf1, int bit_lo, int bit_hi, PipeWork &w) {
+    const uint64_t C = F * (uint64_t)k;
+    if (C == 0) return buf0;
+    if (bit_lo >= bit_hi) {
+        launch_expand(frontier, F, d_gsel, k, buf0, w);
+        return buf0;
+    }
+    w.ensure_status(expand_sort_status_words(F, k));
+    const ExpandSrc src{frontier, F, d_gsel, (uint32_t)k};
+    return run_sort(src, C, buf0, buf1, bit_lo, bit_hi, w, true, 8.0 * (double)F);
+}
+
+}  // namespace cg

@@ -1,0 +1,87 @@
+"""CPU checks of the C ABI: the library loads, exports every declared
+symbol, and rejects bad arguments before touching the device."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2509_19162_amd import _native as N
+from paper_2509_19162_amd import api
+from paper_2509_19162_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in ("cayleygrowth.h", "cayleygrowth_testing.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(cg_[a-z_]+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = N.lib()
+    names = declared_functions()
+    assert {"cg_growth", "cg_growth_ex", "cg_growth_batch", "cg_queue_create"} <= names
+    for name in names:
+        assert hasattr(lib, name), name
+    # the ctypes table covers exactly the declared functions
+    assert {s[0] for s in N.SIGNATURES} == names
+
+
+def test_struct_layout_matches_header():
+    # offsets fixed by the C declaration order on x86-64
+    assert ctypes.sizeof(N.CgJob) == 64
+    assert N.CgResult.layer_sizes.offset == 8
+    assert ctypes.sizeof(N.CgKstat) == 64
+
+
+def test_strerror():
+    lib = N.lib()
+    assert lib.cg_strerror(0) == b"complete"
+    assert lib.cg_strerror(-4) == b"unsupported generating set"
+
+
+@pytest.mark.parametrize(
+    "n,gens,why",
+    [
+        (0, [[0]], "n"),
+        (17, [list(range(17))], "n"),
+        (4, [[0, 1, 2, 2]], "not a permutation"),
+        (4, [[0, 1, 2, 4]], "not a permutation"),
+    ],
+)
+def test_invalid_jobs_are_rejected(n, gens, why):
+    g = np.asarray(gens, dtype=np.uint8)
+    sizes = np.zeros(8, dtype=np.uint64)
+    rc = N.lib().cg_growth(n, g.ctypes.data_as(N.u8p), g.shape[0], 8, sizes.ctypes.data_as(N.u64p))
+    assert rc == N.CG_E_INVAL
+    assert why in N.lib().cg_last_error().decode()
+
+
+def test_zero_generators_and_bad_layers_rejected():
+    g = np.asarray([[1, 0]], dtype=np.uint8)
+    sizes = np.zeros(8, dtype=np.uint64)
+    lib = N.lib()
+    assert lib.cg_growth(2, g.ctypes.data_as(N.u8p), 0, 8, sizes.ctypes.data_as(N.u64p)) == N.CG_E_INVAL
+    assert lib.cg_growth(2, g.ctypes.data_as(N.u8p), 1, 0, sizes.ctypes.data_as(N.u64p)) == N.CG_E_INVAL
+    assert lib.cg_growth(2, g.ctypes.data_as(N.u8p), 1, 8, None) == N.CG_E_INVAL
+
+
+def test_directed_set_needs_flag():
+    with pytest.raises(api.CGError) as e:
+        api.growth(6, I.lx(6))
+    assert e.value.code == N.CG_E_UNSUPPORTED
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(N, "_lib", None)
+    monkeypatch.setattr(N, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(N.NativeLibraryMissing):
+        N.lib()

@@ -1,0 +1,148 @@
+"""Growth on the GPU (through the C ABI) against the CPU oracle, closed
+forms and the paper's printed values. Tolerance: none (exact integers)."""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from golden_data import GOLDEN, binary_coset_growth, mahonian, max_diameter_table, transposition_growth  # noqa: E402
+from oracle import bfs_set  # noqa: E402
+from paper_2509_19162_amd import _native as N  # noqa: E402
+from paper_2509_19162_amd import api  # noqa: E402
+from paper_2509_19162_amd import inputs as I  # noqa: E402
+
+FAMS = ["coxeter", "cyclic_coxeter", "all_transpositions", "star", "pancake", "lrx", "reversals",
+        "transposons", "three_cycles"]
+
+
+def test_bubble_sort_graph_s8():
+    """S_8 with the 7 adjacent transpositions: Mahonian layers, diameter 28."""
+    sizes = api.growth(8, I.coxeter(8))
+    assert sizes == mahonian(8)
+    assert len(sizes) - 1 == 28 and sum(sizes) == 40320
+
+
+@pytest.mark.parametrize("fam", FAMS)
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 7, 8, 9])
+def test_families_match_oracle(fam, n, oracle_c):
+    gens = I.family(fam, n)
+    if not gens:
+        pytest.skip("empty family")
+    expected, rc, _ = oracle_c.growth(n, gens)
+    r = api.growth_ex(n, gens)
+    assert r.sizes == expected and r.status == rc == 0
+
+
+@pytest.mark.parametrize("n", [10, 11, 12])
+def test_closed_forms_beyond_the_python_oracle(n):
+    assert api.growth(n, I.coxeter(n), max_layers=100) == mahonian(n)
+    if n <= 11:
+        assert api.growth(n, I.all_transpositions(n)) == transposition_growth(n)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_sets_match_oracle(seed, oracle_c):
+    rng = I.rng_for(seed, seed=7)
+    n = int(rng.integers(5, 10))
+    gens = I.random_perms_with_inverses(n, int(rng.integers(1, 4)), rng)
+    expected, _, _ = oracle_c.growth(n, gens)
+    assert api.growth(n, gens, max_layers=4096) == expected
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_layer_contents_match_oracle(seed):
+    rng = I.rng_for(100 + seed, seed=7)
+    n = 6 + seed % 3
+    gens = I.random_involutions(n, 3, rng)
+    layers, complete = bfs_set.bfs_layers(n, gens)
+    total = sum(len(x) for x in layers)
+    r = api.growth_ex(n, gens, export_layers=total)
+    assert complete and r.status == N.CG_OK
+    assert r.sizes == [len(x) for x in layers]
+    for got, exp in zip(r.layers, layers):
+        exp_sorted = np.array(sorted(exp), dtype=np.uint8)
+        assert np.array_equal(got, exp_sorted)
+
+
+@pytest.mark.parametrize("row", max_diameter_table(directed=False), ids=lambda r: f"n{r[0]}")
+def test_paper_max_diameters(row):
+    n, diam, gens = row
+    if n > 12:
+        pytest.skip("S_13 and larger run in the long GPU suite")
+    r = api.growth_ex(n, gens, max_layers=512)
+    assert r.status == N.CG_OK
+    assert len(r.sizes) - 1 == diam
+    assert sum(r.sizes) == math.factorial(n)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_metamorphic_invariance(seed, oracle_c):
+    rng = I.rng_for(200 + seed, seed=7)
+    n = int(rng.integers(7, 11))
+    gens = I.random_perms_with_inverses(n, 2, rng)
+    base = api.growth_ex(n, gens, max_layers=4096)
+    start = [int(x) for x in rng.permutation(n)]
+    assert api.growth_ex(n, gens, max_layers=4096, start=start).sizes == base.sizes
+    h = [int(x) for x in rng.permutation(n)]
+    conj = [I.compose(I.compose(I.inverse(h), g), h) for g in gens]
+    assert api.growth_ex(n, conj, max_layers=4096).sizes == base.sizes
+    shuffled = [gens[i] for i in rng.permutation(len(gens))] + gens[:2] + [list(range(n))]
+    assert api.growth_ex(n, shuffled, max_layers=4096).sizes == base.sizes
+    assert api.growth_ex(n, gens, max_layers=4096, keep_all_layers=True).sizes == base.sizes
+
+
+def test_stop_rules_match_oracle(oracle_c):
+    gens = I.lrx(10)
+    for ml in (1, 2, 7, 20):
+        exp, rc, _ = oracle_c.growth(10, gens, max_layers=ml)
+        r = api.growth_ex(10, gens, max_layers=ml)
+        assert r.sizes == exp and r.status == rc
+    for mf in (1, 100, 5000):
+        exp, rc, _ = oracle_c.growth(10, gens, max_frontier=mf)
+        r = api.growth_ex(10, gens, max_frontier=mf, max_layers=4096)
+        assert r.sizes == exp and r.status == rc == N.CG_TRUNCATED
+
+
+def test_degenerate_inputs():
+    assert api.growth(1, [[0]]) == [1]
+    assert api.growth(4, [[0, 1, 2, 3]]) == [1]
+    assert api.growth(2, [[1, 0]]) == [1, 1]
+    r = api.growth_ex(5, I.coxeter(5), max_layers=1)
+    assert r.sizes == [1] and r.status == N.CG_TRUNCATED
+
+
+@pytest.mark.parametrize("fam", ["reversals", "transposons"])
+@pytest.mark.parametrize("n", [6, 9, 12, 16])
+def test_binary_coset_start(fam, n, oracle_c):
+    start = I.binary_central_state(n)
+    gens = I.family(fam, n)
+    r = api.growth_ex(n, gens, start=start, max_layers=64)
+    if n <= 12:
+        exp, rc, _ = oracle_c.growth(n, gens, start=start)
+        assert r.sizes == exp
+    assert r.sizes == binary_coset_growth(n)
+
+
+def _stored(name):
+    path = os.path.join(GOLDEN, "oracle_growth.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle fixtures not generated")
+    with open(path) as f:
+        d = json.load(f)
+    if name not in d:
+        pytest.skip(f"{name} not in oracle fixtures")
+    return d[name]
+
+
+def test_pancake_s12_full_growth_matches_oracle():
+    """S_12 with the 11 prefix reversals, every layer kept on the device."""
+    exp = _stored("pancake_12")
+    r = api.growth_ex(12, I.pancake(12), keep_all_layers=True)
+    assert r.status == N.CG_OK
+    assert r.sizes == exp["sizes"]
+    assert sum(r.sizes) == math.factorial(12)
