@@ -151,6 +151,19 @@ int cg_growth(int n, const uint8_t *gens, int n_gens, int max_layers,
 int cg_growth_ex(const cg_job_t *job, cg_result_t *res, void *stream);
 
 /*
+ * A reusable engine: a stream plus device buffers kept between runs, so
+ * that repeated jobs (benchmark steps, a worker serving many requests) do
+ * not allocate per call. cg_engine_run has the semantics of cg_growth_ex.
+ * One engine runs one job at a time; calls on one engine from several
+ * threads are serialised by the caller. cg_engine_create returns NULL on
+ * failure (see cg_last_error). cg_engine_destroy frees the buffers.
+ */
+typedef struct cg_engine cg_engine_t;
+cg_engine_t *cg_engine_create(void *stream);
+int cg_engine_run(cg_engine_t *eng, const cg_job_t *job, cg_result_t *res);
+void cg_engine_destroy(cg_engine_t *eng);
+
+/*
  * Batch options.
  *   stream         hipStream_t or NULL
  *   max_active     most jobs advanced together in one super-step (0 = auto)

@@ -96,6 +96,9 @@ class CgQueueOpts(ctypes.Structure):
 SIGNATURES = [
     ("cg_growth", ctypes.c_int, [ctypes.c_int, u8p, ctypes.c_int, ctypes.c_int, u64p]),
     ("cg_growth_ex", ctypes.c_int, [ctypes.POINTER(CgJob), ctypes.POINTER(CgResult), ctypes.c_void_p]),
+    ("cg_engine_create", ctypes.c_void_p, [ctypes.c_void_p]),
+    ("cg_engine_run", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CgJob), ctypes.POINTER(CgResult)]),
+    ("cg_engine_destroy", None, [ctypes.c_void_p]),
     ("cg_growth_batch", ctypes.c_int,
      [ctypes.c_int, ctypes.POINTER(CgJob), ctypes.POINTER(CgResult), ctypes.POINTER(CgBatchOpts)]),
     ("cg_queue_create", ctypes.c_void_p, [ctypes.POINTER(CgQueueOpts)]),

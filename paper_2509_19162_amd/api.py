@@ -153,6 +153,36 @@ def growth_ex(n: int, gens: Sequence[Sequence[int]], max_layers: int = 256,
     return h.result()
 
 
+class Engine:
+    """A reusable engine (``cg_engine_*``): keeps its stream and device
+    buffers between runs. ``run`` takes the arguments of ``growth_ex``."""
+
+    def __init__(self, stream=None):
+        self._e = N.lib().cg_engine_create(_stream_handle(stream))
+        if not self._e:
+            raise CGError(N.CG_E_DEVICE, N.lib().cg_last_error().decode())
+
+    def run(self, n: int, gens, max_layers: int = 256, max_frontier: Optional[int] = None,
+            start=None, keep_all_layers: bool = False, allow_directed: bool = False,
+            profile: bool = False, export_layers: int = 0) -> GrowthResult:
+        flags = (N.CG_KEEP_ALL_LAYERS if keep_all_layers else 0) | \
+                (N.CG_ALLOW_DIRECTED if allow_directed else 0) | (N.CG_PROFILE if profile else 0)
+        h = _JobHolder(n, gens, max_layers, max_frontier, flags, start, export_layers)
+        _check(N.lib().cg_engine_run(self._e, ctypes.byref(h.job), ctypes.byref(h.res)))
+        return h.result()
+
+    def close(self):
+        if self._e:
+            N.lib().cg_engine_destroy(self._e)
+            self._e = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def growth_batch(jobs, max_layers: int = 256, max_active: int = 0, budget_bytes: int = 0,
                  tune: bool = True, stream=None) -> List[GrowthResult]:
     """Many independent jobs in shared super-steps (``cg_growth_batch``).

@@ -80,6 +80,36 @@ int cg_growth(int n, const uint8_t *gens, int n_gens, int max_layers, uint64_t *
     return cg_growth_ex(&job, &res, nullptr);
 }
 
+struct cg_engine {
+    cg::Engine eng;
+    explicit cg_engine(hipStream_t s) : eng(s) {}
+};
+
+cg_engine_t *cg_engine_create(void *stream) {
+    cg_engine_t *e = nullptr;
+    const int rc = guarded([&]() -> int {
+        e = new cg_engine((hipStream_t)stream);
+        return CG_OK;
+    });
+    return rc == CG_OK ? e : nullptr;
+}
+
+int cg_engine_run(cg_engine_t *e, const cg_job_t *job, cg_result_t *res) {
+    return guarded([&]() -> int {
+        if (!e || !job || !res || !res->layer_sizes) throw cg::Error(CG_E_INVAL, "NULL engine, job or result");
+        const cg::JobSpec spec = cg::canonicalize(*job, false);
+        e->eng.run(spec, res);
+        return res->status;
+    });
+}
+
+void cg_engine_destroy(cg_engine_t *e) {
+    guarded([&]() -> int {
+        delete e;
+        return CG_OK;
+    });
+}
+
 // ---- kernel-level test entry points -------------------------------------------
 
 int cg_test_pack(int n, const uint8_t *h_states, uint64_t count, uint64_t *d_keys, void *stream) {
