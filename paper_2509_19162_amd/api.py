@@ -187,13 +187,16 @@ def growth_batch(jobs, max_layers: int = 256, max_active: int = 0, budget_bytes:
                  tune: bool = True, stream=None) -> List[GrowthResult]:
     """Many independent jobs in shared super-steps (``cg_growth_batch``).
 
-    ``jobs``: a list of ``(n, gens)`` or ``(n, gens, max_frontier)``.
+    ``jobs``: a list of ``(n, gens)``, ``(n, gens, max_frontier)`` or
+    ``(n, gens, max_frontier, max_layers)``. Per-job failures (a bad
+    generator row) show up as a negative ``status`` in that job's result.
     """
     holders = []
     for j in jobs:
         n, gens = j[0], j[1]
         mf = j[2] if len(j) > 2 else None
-        holders.append(_JobHolder(n, gens, max_layers, mf, 0, None, 0))
+        ml = j[3] if len(j) > 3 and j[3] else max_layers
+        holders.append(_JobHolder(n, gens, ml, mf, 0, None, 0))
     JobArr = N.CgJob * len(holders)
     ResArr = N.CgResult * len(holders)
     ja = JobArr(*[h.job for h in holders])

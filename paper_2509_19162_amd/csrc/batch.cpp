@@ -1,24 +1,296 @@
-// Batched growth and the serving queue (job-tagged keys, shared super-steps).
-#include "../../include/cayleygrowth.h"
-#include "engine.h"
+// Batched growth (cg_growth_batch): independent jobs share super-steps.
+//
+// Workload shape: the paper's searches over many generating sets (section
+// "Largest diameters found (and known) for n <= 15", exhaustive below n = 10
+// and randomised above) run thousands of small, uneven growth jobs. One
+// super-step advances every running job of a group by one layer with a
+// single expand, sort, unique + set difference and compaction over
+// job-tagged keys; a job's result equals its stand-alone result because
+// tags keep the jobs' states apart.
+#include "batch.h"
 
-extern "C" {
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
 
-int cg_growth_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results,
-                    const cg_batch_opts_t *opts) {
-    (void)n_jobs; (void)jobs; (void)results; (void)opts;
-    return CG_E_UNSUPPORTED;
+namespace cg {
+
+BatchGroup::BatchGroup(hipStream_t stream, int n_max, int slots) : stream_(stream), n_max_(n_max) {
+    if (slots < 1) slots = 1;
+    tag_bits_ = 0;
+    while ((1 << tag_bits_) < slots) ++tag_bits_;
+    shift_ = 4 * n_max;
+    if (shift_ + tag_bits_ > 64) throw Error(CG_E_INVAL, "too many jobs for the key width of this n");
+    slot_.resize(slots);
+    quarantine_.assign(slots, 0);
+    w_.init(stream_);
+    host_cap_ = (size_t)slots + 8;
+    CG_HIP(hipHostMalloc((void **)&host_, host_cap_ * sizeof(uint64_t), hipHostMallocDefault));
+    cnt_.ensure((size_t)slots * sizeof(uint64_t));
+    jobs_.ensure((size_t)slots * sizeof(BatchJobDev));
+    for (int i = 0; i < 3; ++i) lay_[i].ensure(1024);
 }
 
-cg_queue_t *cg_queue_create(const cg_queue_opts_t *opts) { (void)opts; return nullptr; }
-int cg_queue_submit(cg_queue_t *q, const cg_job_t *job, cg_result_t *res_slot, uint64_t *ticket) {
-    (void)q; (void)job; (void)res_slot; (void)ticket; return CG_E_UNSUPPORTED;
+BatchGroup::~BatchGroup() {
+    (void)hipStreamSynchronize(stream_);
+    if (host_) (void)hipHostFree(host_);
 }
-int cg_queue_poll(cg_queue_t *q, uint64_t ticket) { (void)q; (void)ticket; return CG_E_UNSUPPORTED; }
-int cg_queue_wait(cg_queue_t *q, uint64_t ticket, int64_t timeout_us) {
-    (void)q; (void)ticket; (void)timeout_us; return CG_E_UNSUPPORTED;
-}
-int cg_queue_cancel(cg_queue_t *q, uint64_t ticket) { (void)q; (void)ticket; return CG_E_UNSUPPORTED; }
-void cg_queue_destroy(cg_queue_t *q) { (void)q; }
 
+int BatchGroup::free_slot() const {
+    for (int s = 0; s < (int)slot_.size(); ++s)
+        if (!slot_[s].res && quarantine_[s] == 0) return s;
+    return -1;
 }
+
+bool BatchGroup::idle() const {
+    for (auto &j : slot_)
+        if (j.res) return false;
+    return pending_keys_.empty();
+}
+
+uint64_t BatchGroup::device_bytes() const {
+    uint64_t b = cand0_.bytes + cand1_.bytes + merged_.bytes + join_.bytes + w_.status.bytes;
+    for (int i = 0; i < 3; ++i) b += lay_[i].bytes;
+    return b;
+}
+
+void BatchGroup::add(int slot, const JobSpec &spec, cg_result_t *res, double t_submit, double t_admit) {
+    if (slot < 0 || slot >= (int)slot_.size() || slot_[slot].res || quarantine_[slot])
+        throw Error(CG_E_INVAL, "slot not free");
+    if (spec.n > n_max_) throw Error(CG_E_INVAL, "job n exceeds the group's n");
+    SlotJob &J = slot_[slot];
+    J = SlotJob{};
+    J.spec = spec;
+    J.res = res;
+    J.t_submit = t_submit;
+    J.t_admit = t_admit;
+    J.F = 0;  // its start key joins the frontier at the next step
+    J.layers = 1;
+    std::memset(res->layer_sizes, 0, sizeof(uint64_t) * (size_t)spec.max_layers);
+    res->layer_sizes[0] = 1;
+    res->states_expanded = 0;
+    res->candidates = 0;
+    res->n_kstats = 0;
+    res->device_ms = 0;
+    const uint64_t tag = shift_ >= 64 ? 0 : ((uint64_t)slot << shift_);
+    J.key0 = tag | pack_host(spec.n, spec.start);
+    pending_keys_.push_back(J.key0);
+    sel_dirty_ = true;
+}
+
+void BatchGroup::finish(int slot, int status) {
+    SlotJob &J = slot_[slot];
+    cg_result_t *r = J.res;
+    r->status = status;
+    r->num_layers = J.layers;
+    r->t_submit = J.t_submit;
+    r->t_admit = J.t_admit;
+    r->t_done = now_seconds();
+    J.res = nullptr;
+    J.done = true;
+    quarantine_[slot] = 3;  // its keys may still sit in layers d and d-1
+    sel_dirty_ = true;
+}
+
+void BatchGroup::cancel(int slot) {
+    if (occupied(slot)) finish(slot, CG_E_CANCELLED);
+}
+
+void BatchGroup::rebuild_gensel() {
+    hsel_.clear();
+    for (auto &J : slot_) {
+        J.goff = (uint32_t)hsel_.size();
+        if (!J.res) continue;
+        for (int g = 0; g < J.spec.k; ++g) hsel_.push_back(make_gensel(J.spec.n, J.spec.gens.data() + (size_t)g * J.spec.n));
+    }
+    if (hsel_.empty()) hsel_.push_back(GenSel{});
+    gsel_.ensure(sizeof(GenSel) * hsel_.size(), 1.5);
+    CG_HIP(hipMemcpyAsync(gsel_.p, hsel_.data(), sizeof(GenSel) * hsel_.size(), hipMemcpyHostToDevice, stream_));
+    sel_dirty_ = false;
+}
+
+void BatchGroup::step(std::vector<int> &finished) {
+    finished.clear();
+    // 1. joining jobs: their start keys merge into the current layer
+    if (!pending_keys_.empty()) {
+        std::sort(pending_keys_.begin(), pending_keys_.end());
+        const uint64_t np = pending_keys_.size();
+        join_.ensure(np * sizeof(uint64_t), 1.5);
+        CG_HIP(hipMemcpyAsync(join_.p, pending_keys_.data(), np * sizeof(uint64_t), hipMemcpyHostToDevice,
+                              stream_));
+        merged_.ensure((ncur_ + np) * sizeof(uint64_t), 1.5);
+        launch_merge(lay_[ic_].as<uint64_t>(), ncur_, join_.as<uint64_t>(), np, merged_.as<uint64_t>(), stream_);
+        std::swap(lay_[ic_].p, merged_.p);
+        std::swap(lay_[ic_].bytes, merged_.bytes);
+        ncur_ += np;
+        for (auto &J : slot_)
+            if (J.res && J.F == 0 && J.layers == 1 && !J.done) J.F = 1;
+        CG_HIP(hipStreamSynchronize(stream_));  // pending_keys_ is host memory
+        pending_keys_.clear();
+    }
+    if (sel_dirty_) rebuild_gensel();
+
+    // 2. stop rules, job table
+    const int S = (int)slot_.size();
+    std::vector<BatchJobDev> tab(S);
+    uint64_t foff = 0, coff = 0;
+    bool any = false;
+    for (int s = 0; s < S; ++s) {
+        SlotJob &J = slot_[s];
+        BatchJobDev &d = tab[s];
+        d.front_off = foff;
+        d.cand_off = coff;
+        d.goff = J.goff;
+        d.kk = 0;
+        if (J.res) {
+            const bool stop = J.layers >= J.spec.max_layers ||
+                              (J.spec.max_frontier && J.F > J.spec.max_frontier) || J.spec.k == 0;
+            if (stop) {
+                finish(s, J.spec.k == 0 ? CG_OK : CG_TRUNCATED);
+                finished.push_back(s);
+            } else {
+                d.kk = (uint32_t)J.spec.k;
+                any = true;
+            }
+        }
+        foff += J.F;
+        coff += (uint64_t)d.kk * J.F;
+    }
+    if (foff != ncur_) throw Error(CG_E_DEVICE, "batch bookkeeping: frontier size mismatch");
+    const uint64_t C = coff;
+    if (!any) {
+        // nothing expands: the layers rotate empty so lingering keys age out
+        for (auto &J : slot_) J.F = 0;
+        std::swap(ip_, ic_);
+        nprev_ = ncur_;
+        ncur_ = 0;
+        for (int s = 0; s < S; ++s)
+            if (quarantine_[s]) --quarantine_[s];
+        return;
+    }
+    CG_HIP(hipMemcpyAsync(jobs_.p, tab.data(), sizeof(BatchJobDev) * S, hipMemcpyHostToDevice, stream_));
+
+    // 3. expand, sort, unique + set difference, compaction, per-job counts
+    cand0_.ensure(C * sizeof(uint64_t) + 64, 1.25);
+    cand1_.ensure(C * sizeof(uint64_t) + 64, 1.25);
+    lay_[in_].ensure(C * sizeof(uint64_t) + 64, 1.25);
+    launch_batch_expand(lay_[ic_].as<uint64_t>(), ncur_, jobs_.as<BatchJobDev>(), gsel_.as<GenSel>(),
+                        cand0_.as<uint64_t>(), shift_, C, (uint32_t)S, w_);
+    const int hi = std::min(64, shift_ + tag_bits_);
+    uint64_t *sorted = radix_sort(cand0_.as<uint64_t>(), cand1_.as<uint64_t>(), C, 4, hi, w_);
+    uint64_t *scratch = sorted == cand0_.as<uint64_t>() ? cand1_.as<uint64_t>() : cand0_.as<uint64_t>();
+    launch_dedup(sorted, C, lay_[ic_].as<uint64_t>(), ncur_, lay_[ip_].as<uint64_t>(), nprev_,
+                 lay_[in_].as<uint64_t>(), C, scratch, w_.counter(), w_);
+    // the new layer's size is needed before counting its tags
+    CG_HIP(hipMemcpyAsync(host_, w_.counter(), sizeof(uint64_t), hipMemcpyDeviceToHost, stream_));
+    CG_HIP(hipMemcpyAsync(host_ + 1, w_.err(), sizeof(uint32_t), hipMemcpyDeviceToHost, stream_));
+    CG_HIP(hipStreamSynchronize(stream_));
+    const uint64_t N = host_[0];
+    if (((uint32_t *)(host_ + 1))[0] != 0) throw Error(CG_E_DEVICE, "kernel error flag set in a batch step");
+    if (N > C) throw Error(CG_E_DEVICE, "batch layer size out of range");
+    launch_tag_count(lay_[in_].as<uint64_t>(), N, shift_, cnt_.as<unsigned long long>(), (uint32_t)S, w_);
+    CG_HIP(hipMemcpyAsync(host_ + 2, cnt_.p, sizeof(uint64_t) * S, hipMemcpyDeviceToHost, stream_));
+    CG_HIP(hipMemcpyAsync(host_ + 1, w_.err(), sizeof(uint32_t), hipMemcpyDeviceToHost, stream_));
+    CG_HIP(hipStreamSynchronize(stream_));
+    if (((uint32_t *)(host_ + 1))[0] != 0) throw Error(CG_E_DEVICE, "kernel error flag set in a batch step");
+
+    // 4. per-job bookkeeping
+    uint64_t sum = 0;
+    for (int s = 0; s < S; ++s) {
+        SlotJob &J = slot_[s];
+        const uint64_t Ns = host_[2 + s];
+        sum += Ns;
+        if (tab[s].kk == 0) {
+            if (Ns) throw Error(CG_E_DEVICE, "a job that did not expand produced states");
+            J.F = 0;
+            continue;
+        }
+        J.res->states_expanded += J.F;
+        J.res->candidates += (uint64_t)tab[s].kk * J.F;
+        J.F = Ns;
+        if (Ns == 0) {
+            finish(s, CG_OK);
+            finished.push_back(s);
+        } else {
+            J.res->layer_sizes[J.layers++] = Ns;
+        }
+    }
+    if (sum != N) throw Error(CG_E_DEVICE, "per-job counts do not add up to the layer size");
+    // 5. rotate layers
+    const int t = ip_;
+    ip_ = ic_;
+    ic_ = in_;
+    in_ = t;
+    nprev_ = ncur_;
+    ncur_ = N;
+    for (int s = 0; s < S; ++s)
+        if (quarantine_[s] && !slot_[s].res) --quarantine_[s];
+}
+
+}  // namespace cg
+
+namespace cg {
+
+// Groups of the batch: jobs of one n share a group (a size class), at most
+// `cap` jobs per group.
+void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_batch_opts_t *opts) {
+    const double t0 = now_seconds();
+    hipStream_t stream = opts ? (hipStream_t)opts->stream : nullptr;
+    bool own = false;
+    if (!stream) {
+        CG_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        own = true;
+    }
+    struct Item {
+        int idx;
+        JobSpec spec;
+    };
+    std::map<int, std::vector<Item>> by_n;
+    for (int i = 0; i < n_jobs; ++i) {
+        cg_result_t *r = &results[i];
+        if (!r->layer_sizes) {
+            r->status = CG_E_INVAL;
+            continue;
+        }
+        try {
+            JobSpec s = canonicalize(jobs[i], true);
+            by_n[s.n].push_back({i, std::move(s)});
+        } catch (const Error &e) {
+            r->status = e.code;
+            r->num_layers = 0;
+        }
+    }
+    try {
+        for (auto &kv : by_n) {
+            const int n = kv.first;
+            auto &items = kv.second;
+            int cap = 1;
+            while (4 * n + 1 + (int)std::log2((double)cap) <= 64 && cap < 4096) cap <<= 1;
+            if (4 * n >= 64) cap = 1;
+            if (opts && opts->max_active > 0) cap = std::min(cap, opts->max_active);
+            for (size_t base = 0; base < items.size(); base += cap) {
+                const int m = (int)std::min<size_t>(cap, items.size() - base);
+                BatchGroup g(stream, n, m);
+                for (int j = 0; j < m; ++j) {
+                    Item &it = items[base + j];
+                    g.add(j, it.spec, &results[it.idx], t0, now_seconds());
+                }
+                std::vector<int> fin;
+                while (!g.idle()) g.step(fin);
+            }
+        }
+    } catch (...) {
+        if (own) {
+            (void)hipStreamSynchronize(stream);
+            (void)hipStreamDestroy(stream);
+        }
+        throw;
+    }
+    if (own) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipStreamDestroy(stream);
+    }
+}
+
+}  // namespace cg

@@ -9,6 +9,7 @@
 
 #include "../../include/cayleygrowth.h"
 #include "../../include/cayleygrowth_testing.h"
+#include "batch.h"
 #include "engine.h"
 
 namespace {
@@ -78,6 +79,15 @@ int cg_growth(int n, const uint8_t *gens, int n_gens, int max_layers, uint64_t *
     cg_result_t res{};
     res.layer_sizes = out_layer_sizes;
     return cg_growth_ex(&job, &res, nullptr);
+}
+
+int cg_growth_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_batch_opts_t *opts) {
+    return guarded([&]() -> int {
+        if (n_jobs < 0 || (n_jobs > 0 && (!jobs || !results)))
+            throw cg::Error(CG_E_INVAL, "bad batch arguments");
+        cg::run_batch(n_jobs, jobs, results, opts);
+        return CG_OK;
+    });
 }
 
 struct cg_engine {
@@ -204,7 +214,9 @@ int cg_test_dedup(const uint64_t *d_sorted, uint64_t C, const uint64_t *d_a, uin
         hipStream_t s = (hipStream_t)stream;
         cg::PipeWork w;
         w.init(s);
-        cg::launch_dedup(d_sorted, C, d_a, na, d_b, nb, d_out, C, w.counter(), w);
+        cg::DevBuf tmp;
+        tmp.ensure(C * sizeof(uint64_t) + 8);
+        cg::launch_dedup(d_sorted, C, d_a, na, d_b, nb, d_out, C, tmp.as<uint64_t>(), w.counter(), w);
         uint64_t cnt = 0;
         uint32_t err = 0;
         CG_HIP(hipMemcpyAsync(&cnt, w.counter(), sizeof cnt, hipMemcpyDeviceToHost, s));
@@ -235,7 +247,8 @@ int cg_test_layer_step(int n, const uint8_t *h_gens, int k, const uint64_t *d_fr
         const uint64_t *sorted =
             cg::expand_sort(d_frontier, F, gs.as<cg::GenSel>(), k, c0.as<uint64_t>(), c1.as<uint64_t>(),
                             4, 4 * n, w);
-        cg::launch_dedup(sorted, C, d_frontier, F, d_prev, np, d_out, C, w.counter(), w);
+        uint64_t *scratch = sorted == c0.as<uint64_t>() ? c1.as<uint64_t>() : c0.as<uint64_t>();
+        cg::launch_dedup(sorted, C, d_frontier, F, d_prev, np, d_out, C, scratch, w.counter(), w);
         uint64_t cnt = 0;
         uint32_t err = 0;
         CG_HIP(hipMemcpyAsync(&cnt, w.counter(), sizeof cnt, hipMemcpyDeviceToHost, s));

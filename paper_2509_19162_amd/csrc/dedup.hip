@@ -12,13 +12,16 @@
 // One 4096-key tile per block:
 //   * keys load coalesced into LDS; thread t takes keys 16t..16t+15 (a
 //     padded layout keeps these reads free of bank conflicts);
-//   * wave 0 locates the tile's key range in each reference layer with
-//     64-way ballot searches; the matching slice is streamed through LDS
-//     in chunks and every thread merges its 16 sorted keys against it with
-//     a galloping search;
-//   * survivors are counted, block-scanned, offset by a decoupled look-back
-//     over the tiles before, staged in LDS and written out contiguously, so
-//     the new layer comes out sorted.
+//   * a separate small kernel first finds, for every tile, the slice of each
+//     reference layer between the tile's first and last key (binary
+//     searches, one thread each), so no tile waits on a search;
+//   * the slice is streamed through LDS in chunks and every thread looks up
+//     its 16 keys in it with 16 interleaved branchless binary searches;
+//   * survivors are compacted within the tile and parked in a scratch
+//     buffer with their count; no tile waits on another;
+//   * a small scan turns the counts into offsets, and a gather moves each
+//     tile's survivors to their final place, so the new layer comes out
+//     sorted and contiguous.
 #include "internal.h"
 #include "device_util.h"
 
@@ -34,52 +37,45 @@ constexpr int kRef = 2048;            // reference keys per LDS chunk
 
 __device__ __forceinline__ uint32_t pad(uint32_t i) { return i + (i >> 4); }
 
-// First index in [pos, m) of the sorted LDS array `a` with a[idx] >= key,
-// or m; galloping from pos.
-__device__ __forceinline__ uint32_t gallop_lb(const uint64_t *a, uint32_t pos, uint32_t m,
-                                              uint64_t key) {
-    if (pos >= m || a[pos] >= key) return pos;
-    uint32_t lo = pos, step = 1, hi = m;  // a[lo] < key
-    for (;;) {
-        const uint32_t probe = lo + step;
-        if (probe >= m) break;
-        if (a[probe] >= key) {
-            hi = probe;
-            break;
-        }
-        lo = probe;
-        step <<= 1;
-    }
-    uint32_t L = lo + 1, H = hi;  // answer in [L, H]
-    while (L < H) {
-        const uint32_t mid = (L + H) >> 1;
-        if (a[mid] < key)
-            L = mid + 1;
+// bounds[4t + 0/1]: lower bound of tile t's first key / upper bound of its
+// last key in A; bounds[4t + 2/3]: the same in B. One thread per bound; the
+// searches of neighbouring tiles share their upper levels in the caches.
+__global__ __launch_bounds__(256) void tile_bounds_kernel(
+    const uint64_t *__restrict__ S, uint64_t C, const uint64_t *__restrict__ A, uint64_t na,
+    const uint64_t *__restrict__ B, uint64_t nb, uint64_t *__restrict__ bounds, uint32_t ntiles) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 4 * ntiles) return;
+    const uint32_t t = i >> 2, w = i & 3u;
+    const uint64_t *R = w < 2 ? A : B;
+    const uint64_t nr = w < 2 ? na : nb;
+    const bool upper = (w & 1u) != 0;
+    const uint64_t end = ((uint64_t)t + 1) * kTile < C ? ((uint64_t)t + 1) * kTile : C;
+    const uint64_t key = upper ? S[end - 1] : S[(uint64_t)t * kTile];
+    uint64_t lo = 0, hi = nr;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        const uint64_t v = R[mid];
+        if (upper ? (v <= key) : (v < key))
+            lo = mid + 1;
         else
-            H = mid;
+            hi = mid;
     }
-    return L;
+    bounds[i] = lo;
 }
 
-__global__ __launch_bounds__(kBlock) void dedup_kernel(
+// Phase 1: one tile per block (no inter-tile dependency): unique + set
+// difference, survivors compacted within the tile into tmp[tile*kTile ..]
+// and counted in cnt[tile].
+__global__ __launch_bounds__(kBlock) void dedup_local_kernel(
     const uint64_t *__restrict__ S, uint64_t C, const uint64_t *__restrict__ A, uint64_t na,
-    const uint64_t *__restrict__ B, uint64_t nb, uint64_t *__restrict__ out, uint64_t out_cap,
-    uint64_t *__restrict__ out_count, uint64_t *__restrict__ status,
-    uint32_t *__restrict__ ticket, uint32_t epoch, uint32_t ntiles, uint32_t *__restrict__ err) {
+    const uint64_t *__restrict__ B, uint64_t nb, const uint64_t *__restrict__ bounds,
+    uint64_t *__restrict__ tmp, uint32_t *__restrict__ cnt) {
     __shared__ uint64_t s_keys[kTile + kTile / 16];
     __shared__ uint64_t s_ref[kRef];
-    __shared__ uint64_t s_bounds[2];
     __shared__ uint32_t s_scan[kWaves];
-    __shared__ uint32_t s_tile;
-    __shared__ uint64_t s_off;
 
     const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & (kWave - 1);
-    const uint32_t wave = tid / kWave;
-
-    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
+    const uint32_t tile = blockIdx.x;
     const uint64_t base = (uint64_t)tile * kTile;
     const uint64_t left = C - base;
     const uint32_t nvalid = (uint32_t)(left < (uint64_t)kTile ? left : (uint64_t)kTile);
@@ -91,6 +87,15 @@ __global__ __launch_bounds__(kBlock) void dedup_kernel(
     }
     const bool has_prev = base > 0;
     const uint64_t prev_global = has_prev ? S[base - 1] : 0;
+    uint64_t bnd[4] = {0, 0, 0, 0};
+    if (na) {
+        bnd[0] = bounds[4 * (uint64_t)tile];
+        bnd[1] = bounds[4 * (uint64_t)tile + 1];
+    }
+    if (nb) {
+        bnd[2] = bounds[4 * (uint64_t)tile + 2];
+        bnd[3] = bounds[4 * (uint64_t)tile + 3];
+    }
     __syncthreads();
 
     uint64_t k[kIpt];
@@ -113,60 +118,42 @@ __global__ __launch_bounds__(kBlock) void dedup_kernel(
         }
         if (idx < nvalid && (first || k[j] != prev)) keep |= 1u << j;
     }
-    const uint64_t kfirst = s_keys[pad(0)];
-    const uint64_t klast = s_keys[pad(nvalid - 1)];
 
     for (int r = 0; r < 2; ++r) {
         const uint64_t *R = r == 0 ? A : B;
-        const uint64_t nr = r == 0 ? na : nb;
-        if (nr == 0) continue;
-        if (wave == 0) {
-            const uint64_t lo = wave_search(R, nr, kfirst, false);
-            const uint64_t hi = wave_search(R, nr, klast, true);
-            if (lane == 0) {
-                s_bounds[0] = lo;
-                s_bounds[1] = hi;
-            }
-        }
-        __syncthreads();
-        const uint64_t lo = s_bounds[0], hi = s_bounds[1];
-        __syncthreads();
+        const uint64_t lo = bnd[2 * r], hi = bnd[2 * r + 1];
         for (uint64_t c0 = lo; c0 < hi; c0 += kRef) {
             const uint64_t rem = hi - c0;
             const uint32_t m = (uint32_t)(rem < (uint64_t)kRef ? rem : (uint64_t)kRef);
             for (uint32_t i = tid; i < m; i += kBlock) s_ref[i] = R[c0 + i];
             __syncthreads();
             if (keep) {
-                uint32_t pos = 0;
+                // 16 independent branchless lower-bound searches, advanced
+                // in lockstep so their LDS latencies overlap
+                uint32_t pos[kIpt];
+#pragma unroll
+                for (int j = 0; j < kIpt; ++j) pos[j] = 0;
+                uint32_t len = m;
+                while (len > 1) {
+                    const uint32_t half = len >> 1;
+#pragma unroll
+                    for (int j = 0; j < kIpt; ++j)
+                        pos[j] = s_ref[pos[j] + half] < k[j] ? pos[j] + half : pos[j];
+                    len -= half;
+                }
 #pragma unroll
                 for (int j = 0; j < kIpt; ++j) {
-                    if ((keep >> j) & 1u) {
-                        pos = gallop_lb(s_ref, pos, m, k[j]);
-                        if (pos < m && s_ref[pos] == k[j]) keep &= ~(1u << j);
-                    }
+                    const uint64_t v = s_ref[pos[j]];
+                    const uint32_t lb = pos[j] + (v < k[j] ? 1u : 0u);
+                    if (lb < m && s_ref[lb] == k[j]) keep &= ~(1u << j);
                 }
             }
             __syncthreads();
         }
     }
 
-    // compaction
-    const uint32_t cnt = (uint32_t)__popc(keep);
     uint32_t total;
-    const uint32_t toff = block_excl_scan<kWaves>(cnt, s_scan, &total);
-    if (tid == 0) {
-        uint64_t *my = status + tile;
-        uint64_t excl = 0;
-        if (tile == 0) {
-            lb_store(my, lb_word(epoch, kFlagInclusive, total));
-        } else {
-            lb_store(my, lb_word(epoch, kFlagAggregate, total));
-            excl = lb_lookback(status, 1, tile, epoch, err);
-            lb_store(my, lb_word(epoch, kFlagInclusive, excl + total));
-        }
-        s_off = excl;
-        if (tile == ntiles - 1) *out_count = excl + total;
-    }
+    const uint32_t toff = block_excl_scan<kWaves>((uint32_t)__popc(keep), s_scan, &total);
     {
         uint32_t r = toff;
 #pragma unroll
@@ -174,10 +161,74 @@ __global__ __launch_bounds__(kBlock) void dedup_kernel(
             if ((keep >> j) & 1u) s_keys[pad(r++)] = k[j];
     }
     __syncthreads();
-    const uint64_t off = s_off;
-    for (uint32_t i = tid; i < total; i += kBlock) {
-        if (off + i < out_cap)
-            out[off + i] = s_keys[pad(i)];
+    for (uint32_t i = tid; i < total; i += kBlock) tmp[base + i] = s_keys[pad(i)];
+    if (tid == 0) cnt[tile] = total;
+}
+
+// Phase 2: exclusive prefix of the per-tile counts, 1024 tiles per block,
+// blocks chained by a wave-parallel decoupled look-back (uniform work).
+constexpr int kScanBlock = 256;
+constexpr int kScanIpt = 4;
+constexpr int kScanTile = kScanBlock * kScanIpt;
+
+__global__ __launch_bounds__(kScanBlock) void count_scan_kernel(
+    const uint32_t *__restrict__ cnt, uint32_t n, uint64_t *__restrict__ off,
+    uint64_t *__restrict__ total_out, uint64_t *__restrict__ status, uint32_t *__restrict__ ticket,
+    uint32_t epoch, uint32_t nblocks, uint32_t *__restrict__ err) {
+    __shared__ uint64_t s_scan[kScanBlock / kWave];
+    __shared__ uint32_t s_blk;
+    __shared__ uint64_t s_prefix;
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) s_blk = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t blk = s_blk;
+    const uint64_t first = (uint64_t)blk * kScanTile + (uint64_t)tid * kScanIpt;
+    uint64_t v[kScanIpt];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanIpt; ++j) {
+        v[j] = first + j < n ? cnt[first + j] : 0;
+        sum += v[j];
+    }
+    uint64_t block_total;
+    const uint64_t ex = block_excl_scan<kScanBlock / kWave>(sum, s_scan, &block_total);
+    if (tid < kWave) {
+        const uint32_t lane = lane_id();
+        uint64_t prefix = 0;
+        if (blk == 0) {
+            if (lane == 0) lb_store(status + blk, lb_word(epoch, kFlagInclusive, block_total));
+        } else {
+            if (lane == 0) lb_store(status + blk, lb_word(epoch, kFlagAggregate, block_total));
+            prefix = lb_lookback_wave(status, blk, epoch, err);
+            if (lane == 0) lb_store(status + blk, lb_word(epoch, kFlagInclusive, prefix + block_total));
+        }
+        if (lane == 0) {
+            s_prefix = prefix;
+            if (blk == nblocks - 1) *total_out = prefix + block_total;
+        }
+    }
+    __syncthreads();
+    uint64_t run = s_prefix + ex;
+#pragma unroll
+    for (int j = 0; j < kScanIpt; ++j) {
+        if (first + j < n) off[first + j] = run;
+        run += v[j];
+    }
+}
+
+// Phase 3: move each tile's survivors to their final place.
+__global__ __launch_bounds__(kBlock) void gather_kernel(const uint64_t *__restrict__ tmp,
+                                                        const uint32_t *__restrict__ cnt,
+                                                        const uint64_t *__restrict__ off,
+                                                        uint64_t *__restrict__ out, uint64_t out_cap,
+                                                        uint32_t *__restrict__ err) {
+    const uint32_t tile = blockIdx.x;
+    const uint32_t c = cnt[tile];
+    const uint64_t o = off[tile];
+    const uint64_t base = (uint64_t)tile * kTile;
+    for (uint32_t i = threadIdx.x; i < c; i += kBlock) {
+        if (o + i < out_cap)
+            out[o + i] = tmp[base + i];
         else
             atomicOr(err, 4u);  // more survivors than the output holds
     }
@@ -185,22 +236,42 @@ __global__ __launch_bounds__(kBlock) void dedup_kernel(
 
 }  // namespace
 
-uint64_t dedup_status_words(uint64_t C) { return (C + kTile - 1) / kTile; }
+uint64_t dedup_status_words(uint64_t C) {
+    const uint64_t tiles = (C + kTile - 1) / kTile;
+    return (tiles + kScanTile - 1) / kScanTile;
+}
 
 void launch_dedup(const uint64_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,
                   const uint64_t *b, uint64_t nb, uint64_t *out, uint64_t out_cap,
-                  uint64_t *d_count, PipeWork &w) {
+                  uint64_t *tmp, uint64_t *d_count, PipeWork &w) {
     uint32_t *ticket = w.tickets() + 31;
     // clears the ticket and the output count (a kernel, not a memset, so the
     // sequence stays valid inside a captured graph)
     launch_clear(ticket, 1, d_count, 1, w.stream);
     if (C == 0) return;
-    const uint32_t ntiles = (uint32_t)dedup_status_words(C);
-    w.ensure_status(ntiles);
+    const uint32_t ntiles = (uint32_t)((C + kTile - 1) / kTile);
+    const uint32_t nscan = (ntiles + kScanTile - 1) / kScanTile;
+    w.ensure_status(nscan);
+    w.bounds.ensure((size_t)ntiles * 4 * sizeof(uint64_t), 1.25);
+    w.tile_cnt.ensure((size_t)ntiles * sizeof(uint32_t), 1.25);
+    w.tile_off.ensure((size_t)ntiles * sizeof(uint64_t), 1.25);
     const uint32_t epoch = w.next_epoch();
     if (w.prof) w.prof->begin(K_DEDUP);
-    hipLaunchKernelGGL(dedup_kernel, dim3(ntiles), dim3(kBlock), 0, w.stream, sorted, C, a, na, b, nb,
-                       out, out_cap, d_count, w.status.as<uint64_t>(), ticket, epoch, ntiles, w.err());
+    if (na || nb) {
+        hipLaunchKernelGGL(tile_bounds_kernel, dim3((4 * ntiles + 255) / 256), dim3(256), 0, w.stream,
+                           sorted, C, a, na, b, nb, w.bounds.as<uint64_t>(), ntiles);
+        CG_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(dedup_local_kernel, dim3(ntiles), dim3(kBlock), 0, w.stream, sorted, C, a, na,
+                       b, nb, w.bounds.as<const uint64_t>(), tmp, w.tile_cnt.as<uint32_t>());
+    CG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(count_scan_kernel, dim3(nscan), dim3(kScanBlock), 0, w.stream,
+                       w.tile_cnt.as<const uint32_t>(), ntiles, w.tile_off.as<uint64_t>(), d_count,
+                       w.status.as<uint64_t>(), ticket, epoch, nscan, w.err());
+    CG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(gather_kernel, dim3(ntiles), dim3(kBlock), 0, w.stream, tmp,
+                       w.tile_cnt.as<const uint32_t>(), w.tile_off.as<const uint64_t>(), out, out_cap,
+                       w.err());
     CG_HIP(hipGetLastError());
     // algorithmic traffic: candidates and both reference layers are read
     // once; the 8N bytes of the output are added by the caller once N is

@@ -101,28 +101,84 @@ __device__ __forceinline__ uint64_t lb_load(const uint64_t *p) {
 }
 
 // Exclusive prefix of tile `tile` from the words of tiles tile-1, tile-2, ...
-// located at base[t * stride]. Tiles publish in ticket order, so every tile
-// waited on is already running; the wait is still bounded: on overrun the
-// error flag is raised and the (then meaningless) partial sum returned.
+// located at base[t * stride]; four predecessors are read per round so a
+// chain of aggregates costs a quarter of the round trips. Tiles publish in
+// ticket order, so every tile waited on is already running; the wait is
+// still bounded: on overrun the error flag is raised and the (then
+// meaningless) partial sum returned.
 __device__ __forceinline__ uint64_t lb_lookback(const uint64_t *base, uint64_t stride,
                                                 uint32_t tile, uint32_t epoch,
                                                 uint32_t *err) {
     uint64_t excl = 0;
     int64_t t = (int64_t)tile - 1;
     uint32_t spins = 0;
+    const uint64_t zero_incl = lb_word(epoch, kFlagInclusive, 0);
     while (t >= 0) {
-        uint64_t w = lb_load(base + (uint64_t)t * stride);
-        if ((uint32_t)(w >> 48) == epoch) {
-            excl += w & kValueMask;
-            if (((w >> 46) & 3u) == kFlagInclusive) break;
-            --t;
-        } else {
+        uint64_t w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            w[u] = (t - u >= 0) ? lb_load(base + (uint64_t)(t - u) * stride) : zero_incl;
+        int used = 0;
+        bool done = false;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (done || used != u) break;
+            if ((uint32_t)(w[u] >> 48) != epoch) break;
+            excl += w[u] & kValueMask;
+            ++used;
+            if (((w[u] >> 46) & 3u) == kFlagInclusive) done = true;
+        }
+        if (done) break;
+        t -= used;
+        if (used == 0) {
             if (++spins > kSpinLimit) {
                 atomicOr(err, 1u);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
         }
+    }
+    return excl;
+}
+
+// Wave-parallel look-back for one value per tile (words at base[t]): the 64
+// lanes read the words of tiles tile-1 .. tile-64 at once, take the nearest
+// inclusive word and add the aggregates before it; if all 64 are
+// aggregates, they move 64 tiles back. Every lane of the wave must call it;
+// all lanes return the same exclusive prefix. Bounded wait as above.
+__device__ __forceinline__ uint64_t lb_lookback_wave(const uint64_t *base, uint32_t tile,
+                                                     uint32_t epoch, uint32_t *err) {
+    const uint32_t lane = lane_id();
+    uint64_t excl = 0;
+    int64_t top = (int64_t)tile - 1;  // highest tile not yet summed
+    uint32_t spins = 0;
+    while (top >= 0) {
+        const int64_t t = top - (int64_t)lane;
+        uint64_t w = 0;
+        bool ready = true, incl = true;
+        if (t >= 0) {
+            w = lb_load(base + t);
+            ready = (uint32_t)(w >> 48) == epoch;
+            incl = ready && (((w >> 46) & 3u) == kFlagInclusive);
+        }  // lanes before tile 0 act as an inclusive zero
+        const uint64_t m_incl = __ballot(incl);
+        const uint64_t m_ready = __ballot(ready);
+        const uint32_t first = m_incl ? (uint32_t)__ffsll((unsigned long long)m_incl) - 1u : 64u;
+        const uint64_t need = first >= 63u ? ~0ull : ((2ull << first) - 1ull);
+        if ((m_ready & need) == need) {
+            uint64_t v = (lane <= first && t >= 0) ? (w & kValueMask) : 0;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) v += shfl64(v, (lane + d) & 63) * (lane + d < 64);
+            excl += shfl64(v, 0);
+            if (first < 64u) break;
+            top -= 64;
+            continue;
+        }
+        if (++spins > kSpinLimit) {
+            if (lane == 0) atomicOr(err, 1u);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
     }
     return excl;
 }

@@ -271,7 +271,8 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
 
         const uint64_t *sorted = expand_sort(Ld, F, gsel_.as<GenSel>(), k, cand0_.as<uint64_t>(),
                                              cand1_.as<uint64_t>(), bit_lo, bit_hi, w_);
-        launch_dedup(sorted, C, Ld, F, Lp, np, out, out_cap, w_.counter(), w_);
+        uint64_t *scratch = sorted == cand0_.as<uint64_t>() ? cand1_.as<uint64_t>() : cand0_.as<uint64_t>();
+        launch_dedup(sorted, C, Ld, F, Lp, np, out, out_cap, scratch, w_.counter(), w_);
         const uint64_t N = read_counter();
         if (N > C || N > room) throw Error(CG_E_DEVICE, "layer size out of range (device error)");
         if (prof_.on) {

@@ -102,6 +102,9 @@ struct PipeWork {
     DevBuf base;     // uint64 [kMaxPasses][256]: exclusive digit offsets
     DevBuf small;    // uint32 tickets[32], err flag, uint64 counters
     DevBuf status;   // uint64 look-back words: tiles x 256 (sort), tiles (dedup)
+    DevBuf bounds;   // uint64 [tiles][4]: reference-layer slices of dedup tiles
+    DevBuf tile_cnt; // uint32 [tiles]: survivors per dedup tile
+    DevBuf tile_off; // uint64 [tiles]: output offset per dedup tile
     uint32_t epoch = 0;  // 16-bit epoch of the look-back words
     hipStream_t stream = nullptr;
     Profiler *prof = nullptr;
@@ -149,10 +152,11 @@ uint64_t expand_sort_status_words(uint64_t F, int k);
 // ---- dedup.hip ----------------------------------------------------------------
 // Unique + set difference against sorted a[0..na) and b[0..nb) + compaction
 // into out (room for out_cap keys; survivors beyond it are not written and
-// raise the error flag); the number of kept keys lands in *d_count.
+// raise the error flag); the number of kept keys lands in *d_count. tmp is
+// scratch of C keys (it may be the sort's other buffer).
 void launch_dedup(const uint64_t *sorted, uint64_t C, const uint64_t *a,
                   uint64_t na, const uint64_t *b, uint64_t nb, uint64_t *out,
-                  uint64_t out_cap, uint64_t *d_count, PipeWork &w);
+                  uint64_t out_cap, uint64_t *tmp, uint64_t *d_count, PipeWork &w);
 uint64_t dedup_status_words(uint64_t C);
 
 }  // namespace cg

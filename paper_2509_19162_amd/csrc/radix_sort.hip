@@ -10,9 +10,9 @@
 //   1. hist    one read of the keys computes the 8-bit digit histograms of
 //              every pass at once (LDS counters, one flush per block);
 //   2. scan    exclusive prefix of each pass's 256 digit counts;
-//   3. pass p  each 4096-key tile ranks its keys per digit with wave64
-//              ballots (8 ballots build the mask of lanes sharing a digit,
-//              v_mbcnt gives the rank below), publishes its per-digit counts
+//   3. pass p  each 4096-key tile ranks its keys per digit within each
+//              wave64 (an LDS word per digit collects the mask of lanes
+//              sharing it, v_mbcnt gives the rank below), publishes its per-digit counts
 //              as decoupled look-back words, reads the exclusive prefix of
 //              the tiles before it, reorders the tile in LDS by digit and
 //              writes runs of equal digits to consecutive addresses.
@@ -33,7 +33,10 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kIpt = 16;
+#ifndef CG_SORT_IPT
+#define CG_SORT_IPT 16
+#endif
+constexpr int kIpt = CG_SORT_IPT;     // keys per thread
 constexpr int kTile = kBlock * kIpt;  // 4096 keys
 constexpr int kWaveSeg = kWave * kIpt;  // keys owned by one wave
 
@@ -58,8 +61,13 @@ struct ArraySrc {
     __host__ __device__ uint32_t tiles() const { return (uint32_t)((count + kTile - 1) / kTile); }
 };
 
-// Tile t covers frontier block t / k under generator t % k: consecutive
-// tiles share a frontier block, so its reads after the first hit the caches.
+// A tile is one frontier block (kTile states) under one generator. Tiles
+// are numbered so that the k tiles of a block are 8 apart: workgroups are
+// dispatched round-robin over the 8 XCDs, so the tiles sharing a frontier
+// block tend to run on one XCD and re-read the block from its L2. (Any
+// numbering is correct; the candidates' initial order does not matter.)
+constexpr uint32_t kXcds = 8;
+
 struct ExpandSrc {
     const uint64_t *frontier;
     uint64_t F;
@@ -72,8 +80,15 @@ struct ExpandSrc {
         __device__ __forceinline__ uint64_t get(uint32_t i) const { return apply_gensel(p[i], sel); }
     };
     __device__ __forceinline__ Tile tile(uint32_t t) const {
-        const uint32_t b = t / k;
-        const uint32_t g = t - b * k;
+        const uint32_t nblocks = (uint32_t)((F + kTile - 1) / kTile);
+        const uint32_t group = kXcds * k;            // tiles of 8 frontier blocks
+        const uint32_t q = t / group;
+        const uint32_t r = t - q * group;
+        const uint32_t full = nblocks / kXcds;
+        const uint32_t width = q < full ? kXcds : nblocks - full * kXcds;
+        const uint32_t x = r % width;
+        const uint32_t g = r / width;
+        const uint32_t b = q * kXcds + x;
         const uint64_t start = (uint64_t)b * kTile;
         const uint64_t left = F - start;
         return Tile{frontier + start, gsel[g],
@@ -97,14 +112,37 @@ __global__ __launch_bounds__(kBlock) void hist_kernel(Src src, uint32_t ntiles, 
     __shared__ uint32_t s_h[kMaxPasses][kRadix];
     for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kBlock) (&s_h[0][0])[i] = 0;
     __syncthreads();
+    // Keys of neighbouring frontier states share their high digits, so each
+    // thread counts runs of equal digits and adds a run with one atomic:
+    // this keeps lanes from piling onto one LDS counter.
+    uint32_t cur[kMaxPasses], run[kMaxPasses];
+#pragma unroll
+    for (int p = 0; p < kMaxPasses; ++p) {
+        cur[p] = 0;
+        run[p] = 0;
+    }
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const auto T = src.tile(t);
         for (uint32_t i = threadIdx.x; i < T.n; i += kBlock) {
             const uint64_t key = T.get(i);
-            for (int p = 0; p < pd.passes; ++p)
-                atomicAdd(&s_h[p][(uint32_t)(key >> pd.shift[p]) & pd.mask[p]], 1u);
+#pragma unroll
+            for (int p = 0; p < kMaxPasses; ++p) {
+                if (p < pd.passes) {
+                    const uint32_t d = (uint32_t)(key >> pd.shift[p]) & pd.mask[p];
+                    if (d != cur[p]) {
+                        if (run[p]) atomicAdd(&s_h[p][cur[p]], run[p]);
+                        cur[p] = d;
+                        run[p] = 1;
+                    } else {
+                        ++run[p];
+                    }
+                }
+            }
         }
     }
+#pragma unroll
+    for (int p = 0; p < kMaxPasses; ++p)
+        if (p < pd.passes && run[p]) atomicAdd(&s_h[p][cur[p]], run[p]);
     __syncthreads();
     for (int p = 0; p < pd.passes; ++p) {
         const uint32_t c = s_h[p][threadIdx.x];
@@ -143,12 +181,19 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     __shared__ uint32_t s_scan[kWaves];
     __shared__ uint32_t s_tile;
 
+    // the digit masks of the ranking live in s_keys until the scatter
+    uint64_t(*s_match)[kRadix] = reinterpret_cast<uint64_t(*)[kRadix]>(s_keys);
+    static_assert(kWaves * kRadix <= kTile, "match words fit in the key tile");
+
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = tid / kWave;
 
     if (tid == 0) s_tile = atomicAdd(ticket, 1u);
-    for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0;
+    for (int i = tid; i < kWaves * kRadix; i += kBlock) {
+        (&s_cnt[0][0])[i] = 0;
+        (&s_match[0][0])[i] = 0;
+    }
     __syncthreads();
     const uint32_t tile = s_tile;
     const auto T = src.tile(tile);
@@ -163,18 +208,41 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
         const uint32_t i = wave * kWaveSeg + j * kWave + lane;
         key[j] = i < nvalid ? T.get(i) : kSentinel;
     }
+    // Peers (lanes of this wave holding the same digit) come from an LDS
+    // mask per digit: every lane ORs its lane bit into its digit's word,
+    // reads the word back and clears it. LDS instructions of one wave are
+    // processed in issue order, so every read sees all ORs of that row.
+    // A row whose valid lanes share one digit skips the LDS round trip.
     uint32_t rank[kIpt];
 #pragma unroll
     for (int j = 0; j < kIpt; ++j) {
         const uint32_t i = wave * kWaveSeg + j * kWave + lane;
         const bool valid = i < nvalid;
         const uint32_t d = (uint32_t)(key[j] >> shift) & dmask;
-        uint64_t peers = __ballot(valid);
+        const uint64_t vmask = __ballot(valid);
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        uint64_t peers;
+#ifdef CG_SORT_MATCH_BALLOT
+        peers = vmask;
 #pragma unroll
         for (int b = 0; b < kRadixBits; ++b) {
             const bool bit = (d >> b) & 1u;
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
+        }
+        if (false) {
+#else
+        if (__ballot(valid && d == d0) == vmask) {
+#endif
+            peers = vmask;
+        } else {
+            if (valid) atomicOr(&s_match[wave][d], 1ull << lane);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            peers = valid ? s_match[wave][d] : 0ull;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (valid) s_match[wave][d] = 0ull;
         }
         const uint32_t below = mask_rank(peers);
         const uint32_t cnt = (uint32_t)__popcll(peers);
