@@ -196,8 +196,12 @@ int cg_growth_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results,
 typedef struct cg_queue cg_queue_t;
 
 /*
+ * Jobs with n <= 13 share one group of job-tagged keys (continuous
+ * batching: they join and leave at super-step boundaries). Jobs with
+ * n > 13, or whose estimated footprint exceeds a quarter of the budget,
+ * run one at a time on a second lane with its own stream.
  *   hbm_budget_bytes  device bytes the active jobs may use together
- *                     (0 = 80% of free memory at creation)
+ *                     (0 = 60% of free memory at creation)
  *   max_active        most jobs on the device at once (0 = 256)
  *   max_queued        most jobs waiting (0 = 65536); beyond it CG_E_BUSY
  */
@@ -219,15 +223,18 @@ cg_queue_t *cg_queue_create(const cg_queue_opts_t *opts);
 int cg_queue_submit(cg_queue_t *q, const cg_job_t *job, cg_result_t *res_slot,
                     uint64_t *ticket);
 
-/* CG_OK (done; res_slot filled), CG_PENDING, or the job's negative status. */
+/* Once the job is done (res_slot filled): its status (CG_OK, CG_TRUNCATED
+   or negative); before that CG_PENDING. CG_E_INVAL for an unknown ticket. */
 int cg_queue_poll(cg_queue_t *q, uint64_t ticket);
 
 /* Waits up to timeout_us (< 0 = forever). Returns like cg_queue_poll, or
-   CG_E_TIMEOUT. */
+   CG_E_TIMEOUT. A wait that returns the job's status releases the ticket
+   (later calls with it return CG_E_INVAL). */
 int cg_queue_wait(cg_queue_t *q, uint64_t ticket, int64_t timeout_us);
 
 /* Cancels a queued or running job; it retires with CG_E_CANCELLED at the
-   next super-step boundary. Returns CG_OK or CG_E_INVAL (unknown ticket). */
+   next super-step boundary (a job on the large-job lane that has started
+   runs to completion). Returns CG_OK or CG_E_INVAL (unknown ticket). */
 int cg_queue_cancel(cg_queue_t *q, uint64_t ticket);
 
 /* Cancels what is left, drains the engine thread, frees everything. */

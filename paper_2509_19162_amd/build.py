@@ -35,9 +35,9 @@ DEVICE = [
 
 
 def _compile(src: str, obj: str, verbose: bool) -> None:
-    cmd = ["hipcc", "-c", src, "-o", obj] + COMMON
-    if src.endswith(".hip"):
-        cmd = ["hipcc", "-x", "hip", "-c", src, "-o", obj] + COMMON + DEVICE
+    # host sources go through hipcc as well (they include the HIP runtime
+    # headers); every translation unit targets gfx950 only
+    cmd = ["hipcc", "-x", "hip", "-c", src, "-o", obj] + COMMON + DEVICE
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -94,7 +94,14 @@ void BatchGroup::finish(int slot, int status) {
 }
 
 void BatchGroup::cancel(int slot) {
-    if (occupied(slot)) finish(slot, CG_E_CANCELLED);
+    if (!occupied(slot)) return;
+    SlotJob &J = slot_[slot];
+    if (J.F == 0 && J.layers == 1) {
+        // not merged into the frontier yet: withdraw the start key
+        auto it = std::find(pending_keys_.begin(), pending_keys_.end(), J.key0);
+        if (it != pending_keys_.end()) pending_keys_.erase(it);
+    }
+    finish(slot, CG_E_CANCELLED);
 }
 
 void BatchGroup::rebuild_gensel() {

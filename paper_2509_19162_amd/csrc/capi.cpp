@@ -39,6 +39,10 @@ int guarded(F &&f) {
 
 }  // namespace
 
+namespace cg {
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+}  // namespace cg
+
 extern "C" {
 
 const char *cg_strerror(int code) {

@@ -28,6 +28,9 @@ JobSpec canonicalize(const cg_job_t &job, bool batch);
 
 double now_seconds();
 
+// Sets the calling thread's cg_last_error() string.
+void set_last_error(const std::string &msg);
+
 class Engine {
 public:
     explicit Engine(hipStream_t user_stream);

@@ -1,15 +1,287 @@
-// placeholder: serving queue entry points (implemented next)
-#include "../../include/cayleygrowth.h"
+// Serving: a request queue with continuous batching (cg_queue_*).
+//
+// Client threads submit growth jobs; an engine thread admits queued jobs
+// while their estimated device footprint fits the budget, adds them into
+// free slots of a shared group (job-tagged keys, see batch_kernels.hip) at
+// a super-step boundary, runs one super-step for every admitted job, and
+// retires finished jobs (result written, timestamps set, waiters woken).
+// Jobs too large to share a group (n > 13, or an estimate above a quarter
+// of the budget) run one at a time on a second lane with its own stream, so
+// they do not stall the small jobs.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+
+#include "batch.h"
+
+namespace cg {
+
+namespace {
+
+constexpr int kSharedN = 13;  // 4*13 state bits + 12 tag bits = 64
+
+// Upper estimate of a job's peak device bytes: the largest layer is taken
+// as 35% of the orbit (capped by what the stop rules allow), times the
+// three layer windows and two candidate buffers with 25% slack.
+uint64_t estimate_bytes(const JobSpec &s) {
+    double layer = 0.35 * (double)s.orbit_bound;
+    if (s.max_frontier) layer = std::min(layer, (double)s.max_frontier * std::max(1, s.k));
+    if (layer < 1) layer = 1;
+    return (uint64_t)(8.0 * layer * (3.0 + 2.5 * std::max(1, s.k))) + (1u << 20);
+}
+
+}  // namespace
+
+struct QueueReq {
+    uint64_t ticket = 0;
+    JobSpec spec;
+    cg_result_t *res = nullptr;
+    double t_submit = 0;
+    int state = 0;  // 0 queued, 1 running, 2 done
+    int status = CG_PENDING;
+    bool cancel = false;
+    bool big = false;
+    int slot = -1;
+    uint64_t bytes = 0;
+};
+
+}  // namespace cg
+
+struct cg_queue {
+    cg_queue_opts_t opts{};
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread engine, big_lane;
+    bool stopping = false;
+    uint64_t next_ticket = 1;
+    uint64_t budget = 0, in_use = 0;
+    std::deque<cg::QueueReq *> queued, big_queued;
+    std::map<uint64_t, std::unique_ptr<cg::QueueReq>> reqs;
+    std::string fatal;  // non-empty once the engine failed
+
+    void engine_loop();
+    void big_loop();
+    void retire(cg::QueueReq *r, int status);
+};
+
+void cg_queue::retire(cg::QueueReq *r, int status) {
+    // caller holds mu
+    r->state = 2;
+    r->status = status;
+    r->res->status = status;
+    in_use -= std::min(in_use, r->bytes);
+    cv_done.notify_all();
+}
+
+void cg_queue::engine_loop() {
+    hipStream_t stream = nullptr;
+    std::unique_ptr<cg::BatchGroup> group;
+    std::map<int, cg::QueueReq *> by_slot;
+    try {
+        CG_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        const int cap = std::max(1, std::min(opts.max_active > 0 ? opts.max_active : 256, 4096));
+        group.reset(new cg::BatchGroup(stream, cg::kSharedN, cap));
+        std::vector<int> fin;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] { return stopping || !queued.empty() || !group->idle(); });
+                if (stopping && group->idle()) break;
+                // cancellations take effect at this super-step boundary
+                for (auto it = by_slot.begin(); it != by_slot.end();) {
+                    if (it->second->cancel || stopping) {
+                        group->cancel(it->first);
+                        cg::QueueReq *r = it->second;
+                        r->res->t_done = cg::now_seconds();
+                        retire(r, CG_E_CANCELLED);
+                        it = by_slot.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+                // admission: FIFO while a slot and the budget allow
+                while (!stopping && !queued.empty()) {
+                    cg::QueueReq *r = queued.front();
+                    if (r->cancel) {
+                        queued.pop_front();
+                        r->res->t_admit = r->res->t_done = cg::now_seconds();
+                        r->res->t_submit = r->t_submit;
+                        retire(r, CG_E_CANCELLED);
+                        continue;
+                    }
+                    const int slot = group->free_slot();
+                    if (slot < 0) break;
+                    if (in_use + r->bytes > budget && !by_slot.empty()) break;
+                    queued.pop_front();
+                    in_use += r->bytes;
+                    r->state = 1;
+                    r->slot = slot;
+                    group->add(slot, r->spec, r->res, r->t_submit, cg::now_seconds());
+                    by_slot[slot] = r;
+                }
+            }
+            if (!group->idle()) group->step(fin);
+            std::lock_guard<std::mutex> lk(mu);
+            for (int s : fin) {
+                auto it = by_slot.find(s);
+                if (it == by_slot.end()) continue;
+                retire(it->second, it->second->res->status);
+                by_slot.erase(it);
+            }
+        }
+    } catch (const std::exception &e) {
+        std::lock_guard<std::mutex> lk(mu);
+        fatal = e.what();
+        for (auto &kv : by_slot) retire(kv.second, CG_E_DEVICE);
+        for (auto *r : queued) retire(r, CG_E_DEVICE);
+        queued.clear();
+    }
+    group.reset();
+    if (stream) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipStreamDestroy(stream);
+    }
+}
+
+void cg_queue::big_loop() {
+    std::unique_ptr<cg::Engine> eng;
+    for (;;) {
+        cg::QueueReq *r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] { return stopping || !big_queued.empty(); });
+            if (big_queued.empty()) break;
+            r = big_queued.front();
+            big_queued.pop_front();
+            if (r->cancel || stopping) {
+                r->res->t_submit = r->t_submit;
+                r->res->t_admit = r->res->t_done = cg::now_seconds();
+                retire(r, CG_E_CANCELLED);
+                continue;
+            }
+            r->state = 1;
+        }
+        const double t_admit = cg::now_seconds();
+        int status;
+        try {
+            if (!eng) eng.reset(new cg::Engine(nullptr));
+            eng->run(r->spec, r->res);
+            status = r->res->status;
+        } catch (const cg::Error &e) {
+            status = e.code;
+        } catch (...) {
+            status = CG_E_DEVICE;
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        r->res->t_submit = r->t_submit;
+        r->res->t_admit = t_admit;
+        r->res->t_done = cg::now_seconds();
+        retire(r, status);
+    }
+}
 
 extern "C" {
-cg_queue_t *cg_queue_create(const cg_queue_opts_t *opts) { (void)opts; return nullptr; }
+
+cg_queue_t *cg_queue_create(const cg_queue_opts_t *opts) {
+    try {
+        std::unique_ptr<cg_queue> q(new cg_queue());
+        if (opts) q->opts = *opts;
+        size_t free_b = 0, total_b = 0;
+        CG_HIP(hipMemGetInfo(&free_b, &total_b));
+        q->budget = q->opts.hbm_budget_bytes ? q->opts.hbm_budget_bytes : (uint64_t)(0.6 * (double)free_b);
+        q->engine = std::thread([p = q.get()] { p->engine_loop(); });
+        q->big_lane = std::thread([p = q.get()] { p->big_loop(); });
+        return q.release();
+    } catch (const std::exception &e) {
+        cg::set_last_error(e.what());
+        return nullptr;
+    }
+}
+
 int cg_queue_submit(cg_queue_t *q, const cg_job_t *job, cg_result_t *res_slot, uint64_t *ticket) {
-    (void)q; (void)job; (void)res_slot; (void)ticket; return CG_E_UNSUPPORTED;
+    if (!q || !job || !res_slot || !res_slot->layer_sizes || !ticket) return CG_E_INVAL;
+    std::unique_ptr<cg::QueueReq> r(new cg::QueueReq());
+    try {
+        r->spec = cg::canonicalize(*job, true);  // copies gens and start
+    } catch (const cg::Error &e) {
+        cg::set_last_error(e.what());
+        return e.code;
+    }
+    r->res = res_slot;
+    r->t_submit = cg::now_seconds();
+    r->bytes = cg::estimate_bytes(r->spec);
+    res_slot->status = CG_PENDING;
+    std::lock_guard<std::mutex> lk(q->mu);
+    if (!q->fatal.empty() || q->stopping) return CG_E_DEVICE;
+    const int max_q = q->opts.max_queued > 0 ? q->opts.max_queued : 65536;
+    if ((int)(q->queued.size() + q->big_queued.size()) >= max_q) return CG_E_BUSY;
+    r->ticket = q->next_ticket++;
+    r->big = r->spec.n > cg::kSharedN || r->bytes > q->budget / 4;
+    *ticket = r->ticket;
+    cg::QueueReq *p = r.get();
+    q->reqs[r->ticket] = std::move(r);
+    if (p->big) {
+        p->bytes = 0;  // the big lane runs alone; its memory is not shared
+        q->big_queued.push_back(p);
+    } else {
+        q->queued.push_back(p);
+    }
+    q->cv_work.notify_all();
+    return CG_OK;
 }
-int cg_queue_poll(cg_queue_t *q, uint64_t ticket) { (void)q; (void)ticket; return CG_E_UNSUPPORTED; }
+
+int cg_queue_poll(cg_queue_t *q, uint64_t ticket) {
+    if (!q) return CG_E_INVAL;
+    std::lock_guard<std::mutex> lk(q->mu);
+    auto it = q->reqs.find(ticket);
+    if (it == q->reqs.end()) return CG_E_INVAL;
+    return it->second->state == 2 ? it->second->status : CG_PENDING;
+}
+
 int cg_queue_wait(cg_queue_t *q, uint64_t ticket, int64_t timeout_us) {
-    (void)q; (void)ticket; (void)timeout_us; return CG_E_UNSUPPORTED;
+    if (!q) return CG_E_INVAL;
+    std::unique_lock<std::mutex> lk(q->mu);
+    auto it = q->reqs.find(ticket);
+    if (it == q->reqs.end()) return CG_E_INVAL;
+    cg::QueueReq *r = it->second.get();
+    auto done = [&] { return r->state == 2; };
+    if (timeout_us < 0) {
+        q->cv_done.wait(lk, done);
+    } else if (!q->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done)) {
+        return CG_E_TIMEOUT;
+    }
+    const int status = r->status;
+    q->reqs.erase(ticket);  // a finished wait releases the ticket
+    return status;
 }
-int cg_queue_cancel(cg_queue_t *q, uint64_t ticket) { (void)q; (void)ticket; return CG_E_UNSUPPORTED; }
-void cg_queue_destroy(cg_queue_t *q) { (void)q; }
+
+int cg_queue_cancel(cg_queue_t *q, uint64_t ticket) {
+    if (!q) return CG_E_INVAL;
+    std::lock_guard<std::mutex> lk(q->mu);
+    auto it = q->reqs.find(ticket);
+    if (it == q->reqs.end()) return CG_E_INVAL;
+    it->second->cancel = true;
+    q->cv_work.notify_all();
+    return CG_OK;
 }
+
+void cg_queue_destroy(cg_queue_t *q) {
+    if (!q) return;
+    {
+        std::lock_guard<std::mutex> lk(q->mu);
+        q->stopping = true;
+        q->cv_work.notify_all();
+    }
+    if (q->engine.joinable()) q->engine.join();
+    if (q->big_lane.joinable()) q->big_lane.join();
+    delete q;
+}
+
+}  // extern "C"
