@@ -99,12 +99,175 @@ def cpu_baseline(workload: dict, budget_s: float = 20.0):
     }
 
 
+def agg_kstats(results):
+    agg = {}
+    for r in results:
+        for name, k in r.kstats.items():
+            a = agg.setdefault(name, {"launches": 0, "total_ms": 0.0, "alg_bytes": 0.0, "items": 0.0})
+            for f in a:
+                a[f] += k[f]
+    return agg
+
+
+def bench_batch(args):
+    """4096 independent jobs (n ~ U{7..10}, 2-4 uniform random permutations
+    plus their inverses, full growth each) in one cg_growth_batch call,
+    against the same jobs run one at a time through a reusable engine (a
+    sample of them, scaled to jobs/s)."""
+    import torch
+
+    from paper_2509_19162_amd import api
+    from paper_2509_19162_amd import inputs as I
+
+    jobs = I.batch_jobs(4096)[: args.batch_jobs]
+    # warm-up on the same batch: the library's device cache then holds every
+    # buffer the timed runs need (a first hipMalloc of tens of GB alone takes
+    # seconds on this driver)
+    for _ in range(args.warmup):
+        api.growth_batch(jobs, max_layers=512)
+    torch.cuda.synchronize()
+    times, res = [], None
+    for _ in range(args.steps):
+        t = time.perf_counter()
+        res = api.growth_batch(jobs, max_layers=512)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    elapsed = sum(times)
+    states = sum(r.states_expanded for r in res)
+    cands = sum(r.candidates for r in res)
+    # sequential plain runs on the same GPU (a sample of the jobs)
+    eng = api.Engine()
+    sample = jobs[: args.seq_sample]
+    for n, gens in sample[:32]:
+        eng.run(n, gens, max_layers=512)
+    t = time.perf_counter()
+    for n, gens in sample:
+        eng.run(n, gens, max_layers=512)
+    seq_dt = time.perf_counter() - t
+    seq_jobs_s = len(sample) / seq_dt
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import native
+
+        native.build(force=False)
+        t = time.perf_counter()
+        m = 0
+        while time.perf_counter() - t < args.cpu_budget and m < len(jobs):
+            native.growth(*jobs[m])
+            m += 1
+        dt = time.perf_counter() - t
+        cpu = {"value": m / dt, "unit": "jobs/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {m} of the 4096 jobs, single-threaded C hash-set BFS, {dt:.1f} s"}
+    value = len(jobs) * args.steps / elapsed
+    line = {
+        "metric": "batched jobs/sec", "value": round(value, 2), "unit": "jobs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1000 * elapsed / args.steps, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{len(jobs)} jobs, n ~ U{{7..10}}, 2-4 uniform random permutations plus "
+                               "inverses, full growth each (seed 19162)", "jobs": len(jobs),
+                   "states_per_step": states, "candidates_per_step": cands},
+        "states_per_s": round(states * args.steps / elapsed, 1),
+        "sequential_plain": {"jobs_per_s": round(seq_jobs_s, 2), "sample_jobs": len(sample),
+                             "speedup_of_batch": round(value / seq_jobs_s, 1)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_serving(args):
+    """Poisson arrivals of growth requests (n ~ U{6..nmax}; family uniform
+    over all transpositions, star, prefix reversals, LRX, 2-4 random
+    involutions) at rates relative to the measured capacity; p50/p99
+    latency from submit to completion and served states/s, against the
+    one-at-a-time plain path on the same trace."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2509_19162_amd import api
+    from paper_2509_19162_amd import inputs as I
+
+    R = args.requests
+    reqs = [I.serving_request(i, n_lo=6, n_hi=args.serving_nmax) for i in range(R)]
+    # warm up both paths on the whole trace (device buffers end up cached)
+    q = api.GrowthQueue(max_active=256)
+    for t in [q.submit(n, g, max_layers=512) for n, fam, g in reqs]:
+        q.wait(t)
+    eng = api.Engine()
+    for n, fam, g in reqs:
+        eng.run(n, g, max_layers=512)
+    # one-at-a-time plain path on the same requests
+    t0 = time.perf_counter()
+    plain_states = 0
+    for n, fam, g in reqs:
+        plain_states += eng.run(n, g, max_layers=512).states_expanded
+    plain_dt = time.perf_counter() - t0
+    # capacity: every request submitted at once
+    t0 = time.perf_counter()
+    ts = [q.submit(n, g, max_layers=512) for n, fam, g in reqs]
+    for t in ts:
+        q.wait(t)
+    cap_dt = time.perf_counter() - t0
+    mu = R / cap_dt
+    points = {}
+    rng = np.random.default_rng(I.SEED)
+    for ratio in args.ratios:
+        lam = ratio * mu
+        gaps = rng.exponential(1.0 / lam, size=R)
+        tickets = [None] * R
+
+        def producer():
+            nxt = time.perf_counter()
+            for i, (n, fam, g) in enumerate(reqs):
+                nxt += gaps[i]
+                d = nxt - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = q.submit(n, g, max_layers=512)
+
+        t0 = time.perf_counter()
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        out = [q.wait(t) for t in tickets]
+        dt = time.perf_counter() - t0
+        lat = np.array([r.t_done - r.t_submit for r in out]) * 1000.0
+        wait = np.array([r.t_admit - r.t_submit for r in out]) * 1000.0
+        states = sum(r.states_expanded for r in out)
+        points[str(ratio)] = {"lambda_req_s": round(lam, 2), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                              "p99_ms": round(float(np.percentile(lat, 99)), 2),
+                              "admit_wait_p50_ms": round(float(np.percentile(wait, 50)), 2),
+                              "states_per_s": round(states / dt, 1)}
+    q.close()
+    torch.cuda.synchronize()
+    ref = points.get("0.9") or list(points.values())[-1]
+    line = {
+        "metric": "p99 job latency", "value": ref["p99_ms"], "unit": "ms", "n_gpus": 1,
+        "steps": len(args.ratios), "warmup": 1, "ms_per_step": round(1000 * cap_dt, 2),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"Poisson stream of {R} growth requests per rate, n ~ U{{6..{args.serving_nmax}}}, "
+                               "families: all transpositions, star, prefix reversals, LRX, 2-4 random "
+                               "involutions; value = p99 at 0.9 x capacity", "requests": R},
+        "capacity_req_per_s": round(mu, 2),
+        "plain_one_at_a_time": {"req_per_s": round(R / plain_dt, 2), "states_per_s": round(plain_states / plain_dt, 1)},
+        "rates": points,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="pancake12", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="pancake12", choices=sorted(WORKLOADS) + ["batch4096", "serving"])
+    ap.add_argument("--seq-sample", type=int, default=256)
+    ap.add_argument("--batch-jobs", type=int, default=4096)
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--serving-nmax", type=int, default=11)
+    ap.add_argument("--ratios", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9, 1.0, 1.2])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
@@ -121,6 +284,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "batch4096":
+        return bench_batch(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     wl = WORKLOADS[args.workload]
     n = wl["n"]
     gens = I.family(wl["family"], n)
@@ -148,12 +315,7 @@ def main():
     value = expanded * args.steps / elapsed
 
     # dominant kernel over the timed region
-    agg = {}
-    for r in results:
-        for name, k in r.kstats.items():
-            a = agg.setdefault(name, {"launches": 0, "total_ms": 0.0, "alg_bytes": 0.0, "items": 0.0})
-            for f in a:
-                a[f] += k[f]
+    agg = agg_kstats(results)
     dom = max(agg, key=lambda k: agg[k]["total_ms"])
     d = agg[dom]
     achieved = d["alg_bytes"] / (d["total_ms"] / 1000.0) / 1e9

@@ -24,7 +24,9 @@
  * Memory: input pointers are host pointers borrowed for the duration of the
  * call (the queue copies what it needs before cg_queue_submit returns).
  * Output arrays are caller-owned host memory. Device memory is owned by the
- * library and released before each call returns (queue: when a job retires).
+ * library; it goes back to the library's device arena when a call returns
+ * (queue: when a job retires) and to the driver on
+ * cg_release_cached_memory().
  */
 #ifndef CAYLEYGROWTH_H
 #define CAYLEYGROWTH_H
@@ -239,6 +241,15 @@ int cg_queue_cancel(cg_queue_t *q, uint64_t ticket);
 
 /* Cancels what is left, drains the engine thread, frees everything. */
 void cg_queue_destroy(cg_queue_t *q);
+
+/*
+ * Device memory: at its first large request the library reserves one
+ * device arena (the fraction CG_ARENA_FRACTION of the free memory, default
+ * 0.85; 0 disables it) and carves every buffer out of it; a freed range is
+ * reused only after the work queued on its last stream has finished. This
+ * returns the arena to the driver if no buffer is in use.
+ */
+void cg_release_cached_memory(void);
 
 /* ---- errors -------------------------------------------------------------- */
 const char *cg_strerror(int code);

@@ -108,6 +108,7 @@ SIGNATURES = [
     ("cg_queue_wait", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64]),
     ("cg_queue_cancel", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     ("cg_queue_destroy", None, [ctypes.c_void_p]),
+    ("cg_release_cached_memory", None, []),
     ("cg_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("cg_last_error", ctypes.c_char_p, []),
     ("cg_test_pack", ctypes.c_int, [ctypes.c_int, u8p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),

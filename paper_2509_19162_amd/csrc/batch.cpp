@@ -25,9 +25,13 @@ BatchGroup::BatchGroup(hipStream_t stream, int n_max, int slots) : stream_(strea
     slot_.resize(slots);
     quarantine_.assign(slots, 0);
     w_.init(stream_);
+    for (DevBuf *b : {&gsel_, &jobs_, &cand0_, &cand1_, &lay_[0], &lay_[1], &lay_[2], &cnt_, &pos_, &join_,
+                      &merged_})
+        b->stream = stream_;
     host_cap_ = (size_t)slots + 8;
     CG_HIP(hipHostMalloc((void **)&host_, host_cap_ * sizeof(uint64_t), hipHostMallocDefault));
     cnt_.ensure((size_t)slots * sizeof(uint64_t));
+    pos_.ensure(((size_t)slots + 1) * sizeof(uint64_t));
     jobs_.ensure((size_t)slots * sizeof(BatchJobDev));
     for (int i = 0; i < 3; ++i) lay_[i].ensure(1024);
 }
@@ -90,7 +94,6 @@ void BatchGroup::finish(int slot, int status) {
     J.res = nullptr;
     J.done = true;
     quarantine_[slot] = 3;  // its keys may still sit in layers d and d-1
-    sel_dirty_ = true;
 }
 
 void BatchGroup::cancel(int slot) {
@@ -181,22 +184,24 @@ void BatchGroup::step(std::vector<int> &finished) {
     // 3. expand, sort, unique + set difference, compaction, per-job counts
     cand0_.ensure(C * sizeof(uint64_t) + 64, 1.25);
     cand1_.ensure(C * sizeof(uint64_t) + 64, 1.25);
-    lay_[in_].ensure(C * sizeof(uint64_t) + 64, 1.25);
     launch_batch_expand(lay_[ic_].as<uint64_t>(), ncur_, jobs_.as<BatchJobDev>(), gsel_.as<GenSel>(),
                         cand0_.as<uint64_t>(), shift_, C, (uint32_t)S, w_);
     const int hi = std::min(64, shift_ + tag_bits_);
     uint64_t *sorted = radix_sort(cand0_.as<uint64_t>(), cand1_.as<uint64_t>(), C, 4, hi, w_);
     uint64_t *scratch = sorted == cand0_.as<uint64_t>() ? cand1_.as<uint64_t>() : cand0_.as<uint64_t>();
-    launch_dedup(sorted, C, lay_[ic_].as<uint64_t>(), ncur_, lay_[ip_].as<uint64_t>(), nprev_,
-                 lay_[in_].as<uint64_t>(), C, scratch, w_.counter(), w_);
-    // the new layer's size is needed before counting its tags
+    launch_dedup_count(sorted, C, lay_[ic_].as<uint64_t>(), ncur_, lay_[ip_].as<uint64_t>(), nprev_, scratch,
+                       w_.counter(), w_);
+    // the new layer is sized once its length is known
     CG_HIP(hipMemcpyAsync(host_, w_.counter(), sizeof(uint64_t), hipMemcpyDeviceToHost, stream_));
     CG_HIP(hipMemcpyAsync(host_ + 1, w_.err(), sizeof(uint32_t), hipMemcpyDeviceToHost, stream_));
     CG_HIP(hipStreamSynchronize(stream_));
     const uint64_t N = host_[0];
     if (((uint32_t *)(host_ + 1))[0] != 0) throw Error(CG_E_DEVICE, "kernel error flag set in a batch step");
     if (N > C) throw Error(CG_E_DEVICE, "batch layer size out of range");
-    launch_tag_count(lay_[in_].as<uint64_t>(), N, shift_, cnt_.as<unsigned long long>(), (uint32_t)S, w_);
+    lay_[in_].ensure(std::max<uint64_t>(N, 1) * sizeof(uint64_t) + 64, 1.25);
+    launch_dedup_gather(scratch, lay_[in_].as<uint64_t>(), N, w_);
+    launch_tag_count(lay_[in_].as<uint64_t>(), N, shift_, cnt_.as<unsigned long long>(),
+                     pos_.as<unsigned long long>(), (uint32_t)S, w_);
     CG_HIP(hipMemcpyAsync(host_ + 2, cnt_.p, sizeof(uint64_t) * S, hipMemcpyDeviceToHost, stream_));
     CG_HIP(hipMemcpyAsync(host_ + 1, w_.err(), sizeof(uint32_t), hipMemcpyDeviceToHost, stream_));
     CG_HIP(hipStreamSynchronize(stream_));
@@ -276,15 +281,29 @@ void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_
             while (4 * n + 1 + (int)std::log2((double)cap) <= 64 && cap < 4096) cap <<= 1;
             if (4 * n >= 64) cap = 1;
             if (opts && opts->max_active > 0) cap = std::min(cap, opts->max_active);
-            for (size_t base = 0; base < items.size(); base += cap) {
-                const int m = (int)std::min<size_t>(cap, items.size() - base);
-                BatchGroup g(stream, n, m);
-                for (int j = 0; j < m; ++j) {
-                    Item &it = items[base + j];
-                    g.add(j, it.spec, &results[it.idx], t0, now_seconds());
+            // groups of at most `cap` jobs; a group that runs out of device
+            // memory is split in half and its jobs start over
+            std::vector<std::pair<size_t, size_t>> todo;
+            for (size_t base = 0; base < items.size(); base += cap)
+                todo.push_back({base, std::min<size_t>(cap, items.size() - base)});
+            while (!todo.empty()) {
+                const auto span = todo.back();
+                todo.pop_back();
+                const int m = (int)span.second;
+                try {
+                    BatchGroup g(stream, n, m);
+                    for (int j = 0; j < m; ++j) {
+                        Item &it = items[span.first + j];
+                        g.add(j, it.spec, &results[it.idx], t0, now_seconds());
+                    }
+                    std::vector<int> fin;
+                    while (!g.idle()) g.step(fin);
+                } catch (const Error &e) {
+                    if (e.code != CG_E_NOMEM || m == 1) throw;
+                    CG_HIP(hipStreamSynchronize(stream));
+                    todo.push_back({span.first + (size_t)m / 2, (size_t)(m - m / 2)});
+                    todo.push_back({span.first, (size_t)m / 2});
                 }
-                std::vector<int> fin;
-                while (!g.idle()) g.step(fin);
             }
         }
     } catch (...) {

@@ -19,8 +19,9 @@ struct BatchJobDev {
 void launch_batch_expand(const uint64_t *frontier, uint64_t total_f, const BatchJobDev *d_jobs,
                          const GenSel *d_gsel, uint64_t *out, int shift, uint64_t total_c,
                          uint32_t nslots, PipeWork &w);
+// Per-slot key counts of a sorted batched layer (d_pos: nslots+1 scratch).
 void launch_tag_count(const uint64_t *keys, uint64_t n, int shift, unsigned long long *d_cnt,
-                      uint32_t nslots, PipeWork &w);
+                      unsigned long long *d_pos, uint32_t nslots, PipeWork &w);
 // out = merge of sorted a[0..na) and sorted b[0..nb) (no key in both).
 void launch_merge(const uint64_t *a, uint64_t na, const uint64_t *b, uint64_t nb, uint64_t *out,
                   hipStream_t s);
@@ -74,7 +75,7 @@ private:
     std::vector<GenSel> hsel_;
     bool sel_dirty_ = true;
     PipeWork w_;
-    DevBuf gsel_, jobs_, cand0_, cand1_, lay_[3], cnt_, join_, merged_;
+    DevBuf gsel_, jobs_, cand0_, cand1_, lay_[3], cnt_, pos_, join_, merged_;
     int ip_ = 0, ic_ = 1, in_ = 2;
     uint64_t nprev_ = 0, ncur_ = 0;  // sizes of layers d-1 and d (all jobs)
     uint64_t *host_ = nullptr;       // pinned: per-slot counts + flags

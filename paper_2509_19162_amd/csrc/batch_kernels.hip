@@ -39,35 +39,38 @@ __global__ __launch_bounds__(256) void batch_expand_kernel(
     for (uint32_t g = 0; g < J.kk; ++g) out[base + g] = tagbits | apply_gensel(s, gsel[J.goff + g]);
 }
 
-// Per-job sizes of a sorted batched layer: each thread takes 16 consecutive
-// keys, counts runs of equal tags and adds each run with one atomic.
-__global__ __launch_bounds__(256) void tag_count_kernel(const uint64_t *__restrict__ keys, uint64_t n,
-                                                        int shift, unsigned long long *__restrict__ cnt,
-                                                        uint32_t nslots, uint32_t *__restrict__ err) {
-    const uint64_t first = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
-    if (first >= n) return;
-    const uint64_t last = first + 16 < n ? first + 16 : n;
-    uint32_t cur = 0xFFFFFFFFu;
-    unsigned long long run = 0;
-    for (uint64_t i = first; i < last; ++i) {
-        const uint32_t slot = shift >= 64 ? 0u : (uint32_t)(keys[i] >> shift);
-        if (slot >= nslots) {
-            atomicOr(err, 16u);
-            return;
-        }
-        if (slot != cur) {
-            if (run) atomicAdd(&cnt[cur], run);
-            cur = slot;
-            run = 0;
-        }
-        ++run;
+// Per-job sizes of a sorted batched layer: the keys of slot s form one run
+// starting at lower_bound(s << shift), so one binary search per slot
+// boundary gives every count without reading the layer.
+__global__ __launch_bounds__(256) void tag_bounds_kernel(const uint64_t *__restrict__ keys, uint64_t n,
+                                                         int shift, uint32_t nslots,
+                                                         unsigned long long *__restrict__ pos) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > nslots) return;
+    if (shift >= 64) {
+        pos[s] = s == 0 ? 0 : n;
+        return;
     }
-    if (run) atomicAdd(&cnt[cur], run);
+    const uint64_t key = s >= nslots ? ~0ull : ((uint64_t)s << shift);
+    if (s >= nslots) {
+        pos[s] = n;
+        return;
+    }
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    pos[s] = lo;
 }
 
-__global__ void clear_u64_kernel(unsigned long long *__restrict__ a, uint32_t n) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = 0;
+__global__ void bounds_to_counts_kernel(const unsigned long long *__restrict__ pos, uint32_t nslots,
+                                        unsigned long long *__restrict__ cnt) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nslots) cnt[s] = pos[s + 1] - pos[s];
 }
 
 // Merge of two sorted arrays with no common key: every element lands at its
@@ -115,13 +118,12 @@ void launch_batch_expand(const uint64_t *frontier, uint64_t total_f, const Batch
 }
 
 void launch_tag_count(const uint64_t *keys, uint64_t n, int shift, unsigned long long *d_cnt,
-                      uint32_t nslots, PipeWork &w) {
-    hipLaunchKernelGGL(clear_u64_kernel, dim3((nslots + 255) / 256), dim3(256), 0, w.stream, d_cnt, nslots);
+                      unsigned long long *d_pos, uint32_t nslots, PipeWork &w) {
+    hipLaunchKernelGGL(tag_bounds_kernel, dim3((nslots + 1 + 255) / 256), dim3(256), 0, w.stream, keys, n,
+                       shift, nslots, d_pos);
     CG_HIP(hipGetLastError());
-    if (!n) return;
-    const uint64_t threads = (n + 15) / 16;
-    hipLaunchKernelGGL(tag_count_kernel, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, w.stream,
-                       keys, n, shift, d_cnt, nslots, w.err());
+    hipLaunchKernelGGL(bounds_to_counts_kernel, dim3((nslots + 255) / 256), dim3(256), 0, w.stream, d_pos,
+                       nslots, d_cnt);
     CG_HIP(hipGetLastError());
 }
 

@@ -63,6 +63,13 @@ const char *cg_strerror(int code) {
 
 const char *cg_last_error(void) { return g_last_error.c_str(); }
 
+void cg_release_cached_memory(void) {
+    guarded([&]() -> int {
+        cg::release_cached_device_memory();
+        return CG_OK;
+    });
+}
+
 int cg_growth_ex(const cg_job_t *job, cg_result_t *res, void *stream) {
     return guarded([&]() -> int {
         if (!job || !res || !res->layer_sizes) throw cg::Error(CG_E_INVAL, "NULL job or result");
@@ -133,6 +140,7 @@ int cg_test_pack(int n, const uint8_t *h_states, uint64_t count, uint64_t *d_key
         if (!count) return CG_OK;
         hipStream_t s = (hipStream_t)stream;
         cg::DevBuf rows;
+        rows.stream = s;
         rows.ensure(count * n);
         CG_HIP(hipMemcpyAsync(rows.p, h_states, count * n, hipMemcpyHostToDevice, s));
         cg::launch_pack(n, rows.as<uint8_t>(), count, d_keys, s);
@@ -148,6 +156,7 @@ int cg_test_unpack(int n, const uint64_t *d_keys, uint64_t count, uint8_t *h_sta
         if (!count) return CG_OK;
         hipStream_t s = (hipStream_t)stream;
         cg::DevBuf rows;
+        rows.stream = s;
         rows.ensure(count * n);
         cg::launch_unpack(n, d_keys, count, rows.as<uint8_t>(), s);
         CG_HIP(hipMemcpyAsync(h_states, rows.p, count * n, hipMemcpyDeviceToHost, s));
@@ -180,6 +189,7 @@ int cg_test_expand(int n, const uint8_t *h_gens, int k, const uint64_t *d_fronti
         cg::PipeWork w;
         w.init(s);
         cg::DevBuf gs;
+        gs.stream = s;
         gs.ensure(sizeof(cg::GenSel) * k);
         CG_HIP(hipMemcpyAsync(gs.p, sels.data(), sizeof(cg::GenSel) * k, hipMemcpyHostToDevice, s));
         cg::launch_expand(d_frontier, F, gs.as<cg::GenSel>(), k, d_out, w);
@@ -219,6 +229,7 @@ int cg_test_dedup(const uint64_t *d_sorted, uint64_t C, const uint64_t *d_a, uin
         cg::PipeWork w;
         w.init(s);
         cg::DevBuf tmp;
+        tmp.stream = s;
         tmp.ensure(C * sizeof(uint64_t) + 8);
         cg::launch_dedup(d_sorted, C, d_a, na, d_b, nb, d_out, C, tmp.as<uint64_t>(), w.counter(), w);
         uint64_t cnt = 0;
@@ -243,6 +254,7 @@ int cg_test_layer_step(int n, const uint8_t *h_gens, int k, const uint64_t *d_fr
         cg::PipeWork w;
         w.init(s);
         cg::DevBuf gs, c0, c1;
+        gs.stream = c0.stream = c1.stream = s;
         gs.ensure(sizeof(cg::GenSel) * k);
         CG_HIP(hipMemcpyAsync(gs.p, sels.data(), sizeof(cg::GenSel) * k, hipMemcpyHostToDevice, s));
         const uint64_t C = F * (uint64_t)k;

@@ -241,13 +241,14 @@ uint64_t dedup_status_words(uint64_t C) {
     return (tiles + kScanTile - 1) / kScanTile;
 }
 
-void launch_dedup(const uint64_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,
-                  const uint64_t *b, uint64_t nb, uint64_t *out, uint64_t out_cap,
-                  uint64_t *tmp, uint64_t *d_count, PipeWork &w) {
+void launch_dedup_count(const uint64_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,
+                        const uint64_t *b, uint64_t nb, uint64_t *tmp, uint64_t *d_count,
+                        PipeWork &w) {
     uint32_t *ticket = w.tickets() + 31;
     // clears the ticket and the output count (a kernel, not a memset, so the
     // sequence stays valid inside a captured graph)
     launch_clear(ticket, 1, d_count, 1, w.stream);
+    w.dedup_tiles = 0;
     if (C == 0) return;
     const uint32_t ntiles = (uint32_t)((C + kTile - 1) / kTile);
     const uint32_t nscan = (ntiles + kScanTile - 1) / kScanTile;
@@ -269,14 +270,28 @@ void launch_dedup(const uint64_t *sorted, uint64_t C, const uint64_t *a, uint64_
                        w.tile_cnt.as<const uint32_t>(), ntiles, w.tile_off.as<uint64_t>(), d_count,
                        w.status.as<uint64_t>(), ticket, epoch, nscan, w.err());
     CG_HIP(hipGetLastError());
-    hipLaunchKernelGGL(gather_kernel, dim3(ntiles), dim3(kBlock), 0, w.stream, tmp,
-                       w.tile_cnt.as<const uint32_t>(), w.tile_off.as<const uint64_t>(), out, out_cap,
-                       w.err());
-    CG_HIP(hipGetLastError());
     // algorithmic traffic: candidates and both reference layers are read
     // once; the 8N bytes of the output are added by the caller once N is
     // known
     if (w.prof) w.prof->end(K_DEDUP, 8.0 * (double)(C + na + nb), (double)C);
+    w.dedup_tiles = ntiles;
+}
+
+void launch_dedup_gather(const uint64_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w) {
+    if (!w.dedup_tiles) return;
+    if (w.prof) w.prof->begin(K_DEDUP);
+    hipLaunchKernelGGL(gather_kernel, dim3(w.dedup_tiles), dim3(kBlock), 0, w.stream, tmp,
+                       w.tile_cnt.as<const uint32_t>(), w.tile_off.as<const uint64_t>(), out, out_cap,
+                       w.err());
+    CG_HIP(hipGetLastError());
+    if (w.prof) w.prof->end(K_DEDUP, 0, 0);
+}
+
+void launch_dedup(const uint64_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,
+                  const uint64_t *b, uint64_t nb, uint64_t *out, uint64_t out_cap,
+                  uint64_t *tmp, uint64_t *d_count, PipeWork &w) {
+    launch_dedup_count(sorted, C, a, na, b, nb, tmp, d_count, w);
+    launch_dedup_gather(tmp, out, out_cap, w);
 }
 
 }  // namespace cg

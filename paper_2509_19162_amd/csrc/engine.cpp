@@ -108,12 +108,17 @@ Engine::Engine(hipStream_t user_stream) {
         own_stream_ = true;
     }
     w_.init(stream_);
+    for (DevBuf *b : {&gsel_, &cand0_, &cand1_, &lay_[0], &lay_[1], &lay_[2], &arena_, &stage_}) b->stream = stream_;
     prof_.stream = stream_;
     CG_HIP(hipHostMalloc((void **)&host_small_, 64, hipHostMallocDefault));
 }
 
 Engine::~Engine() {
     if (host_small_) (void)hipHostFree(host_small_);
+    // buffers go back to the device cache while their stream still exists
+    for (DevBuf *b : {&gsel_, &cand0_, &cand1_, &lay_[0], &lay_[1], &lay_[2], &arena_, &stage_}) b->release();
+    for (DevBuf *b : {&w_.hist, &w_.base, &w_.small, &w_.status, &w_.bounds, &w_.tile_cnt, &w_.tile_off})
+        b->release();
     if (own_stream_) {
         (void)hipStreamSynchronize(stream_);
         (void)hipStreamDestroy(stream_);
@@ -251,6 +256,7 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
                 size_t want = std::max<size_t>(need, (size_t)(arena_.bytes * 1.5));
                 want = std::min<size_t>(want, std::max<size_t>(need, spec.orbit_bound * 8));
                 DevBuf bigger;
+                bigger.stream = stream_;
                 bigger.ensure(want);
                 CG_HIP(hipMemcpyAsync(bigger.p, arena_.p, total * sizeof(uint64_t),
                                       hipMemcpyDeviceToDevice, stream_));
@@ -263,18 +269,22 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             Lp = d > 0 ? arena_.as<uint64_t>() + off[d - 1] : nullptr;
             out = arena_.as<uint64_t>() + total;
         } else {
-            lay_[in].ensure(out_cap * sizeof(uint64_t), 1.25);
             Ld = lay_[ic].as<uint64_t>();
             Lp = lay_[ip].as<uint64_t>();
-            out = lay_[in].as<uint64_t>();
+            out = nullptr;  // sized once N is known
         }
 
         const uint64_t *sorted = expand_sort(Ld, F, gsel_.as<GenSel>(), k, cand0_.as<uint64_t>(),
                                              cand1_.as<uint64_t>(), bit_lo, bit_hi, w_);
         uint64_t *scratch = sorted == cand0_.as<uint64_t>() ? cand1_.as<uint64_t>() : cand0_.as<uint64_t>();
-        launch_dedup(sorted, C, Ld, F, Lp, np, out, out_cap, scratch, w_.counter(), w_);
+        launch_dedup_count(sorted, C, Ld, F, Lp, np, scratch, w_.counter(), w_);
         const uint64_t N = read_counter();
         if (N > C || N > room) throw Error(CG_E_DEVICE, "layer size out of range (device error)");
+        if (!keep_all) {
+            lay_[in].ensure(std::max<uint64_t>(N, 1) * sizeof(uint64_t), 1.25);
+            out = lay_[in].as<uint64_t>();
+        }
+        launch_dedup_gather(scratch, out, keep_all ? out_cap : N, w_);
         if (prof_.on) {
             prof_.collect();
             prof_.bytes[K_DEDUP] += 8.0 * (double)N;
@@ -302,6 +312,7 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
 
     CG_HIP(hipEventRecord(ev1, stream_));
     CG_HIP(hipEventSynchronize(ev1));
+    (void)read_counter();  // surfaces an error flag raised by the last gather
     float ms = 0;
     CG_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     (void)hipEventDestroy(ev0);

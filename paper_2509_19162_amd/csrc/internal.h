@@ -88,14 +88,21 @@ struct Profiler {
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    int dev = 0;
+    bool in_arena = false;
+    hipStream_t stream = nullptr;  // the stream the owner uses the buffer on
     // Grow to at least `need` bytes (contents are not kept). Returns true if
-    // the buffer was reallocated.
+    // the buffer was reallocated. Memory comes from the device arena.
     bool ensure(size_t need, double slack = 1.0);
     void release();
     ~DevBuf() { release(); }
     template <class T>
     T *as() const { return static_cast<T *>(p); }
 };
+
+// Returns the device arena to the driver when no buffer uses it
+// (cg_release_cached_memory).
+void release_cached_device_memory();
 
 struct PipeWork {
     DevBuf hist;     // uint64 [kMaxPasses][256]: digit counts of every pass
@@ -106,6 +113,7 @@ struct PipeWork {
     DevBuf tile_cnt; // uint32 [tiles]: survivors per dedup tile
     DevBuf tile_off; // uint64 [tiles]: output offset per dedup tile
     uint32_t epoch = 0;  // 16-bit epoch of the look-back words
+    uint32_t dedup_tiles = 0;  // tiles of the last launch_dedup_count
     hipStream_t stream = nullptr;
     Profiler *prof = nullptr;
 
@@ -157,6 +165,15 @@ uint64_t expand_sort_status_words(uint64_t F, int k);
 void launch_dedup(const uint64_t *sorted, uint64_t C, const uint64_t *a,
                   uint64_t na, const uint64_t *b, uint64_t nb, uint64_t *out,
                   uint64_t out_cap, uint64_t *tmp, uint64_t *d_count, PipeWork &w);
+// The same in two halves, so the caller can size `out` once N is known:
+// the count half leaves N in *d_count (survivors parked in tmp); the gather
+// half moves them to out.
+void launch_dedup_count(const uint64_t *sorted, uint64_t C, const uint64_t *a,
+                        uint64_t na, const uint64_t *b, uint64_t nb, uint64_t *tmp,
+                        uint64_t *d_count, PipeWork &w);
+void launch_dedup_gather(const uint64_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w);
+// True once the device's arena exists (buffers then grow to exact sizes).
+bool arena_active();
 uint64_t dedup_status_words(uint64_t C);
 
 }  // namespace cg

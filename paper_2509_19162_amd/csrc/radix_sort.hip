@@ -59,6 +59,7 @@ struct ArraySrc {
         return Tile{keys + start, (uint32_t)(left < (uint64_t)kTile ? left : (uint64_t)kTile)};
     }
     __host__ __device__ uint32_t tiles() const { return (uint32_t)((count + kTile - 1) / kTile); }
+    void materialize(uint64_t *, PipeWork &) const {}
 };
 
 // A tile is one frontier block (kTile states) under one generator. Tiles
@@ -97,6 +98,7 @@ struct ExpandSrc {
     __host__ __device__ uint32_t tiles() const {
         return (uint32_t)(((F + kTile - 1) / kTile) * (uint64_t)k);
     }
+    void materialize(uint64_t *out, PipeWork &w) const { launch_expand(frontier, F, gsel, (int)k, out, w); }
 };
 
 struct PassDesc {
@@ -316,10 +318,12 @@ uint32_t hist_grid(uint32_t ntiles) {
     return ntiles < cap ? (ntiles ? ntiles : 1) : cap;
 }
 
+constexpr uint64_t kSkipCheckMin = 1ull << 22;
+
 template <class Src>
 uint64_t *run_sort(const Src &first_src, uint64_t count, uint64_t *buf0, uint64_t *buf1,
                    int bit_lo, int bit_hi, PipeWork &w, bool fused_first,
-                   double first_read_bytes) {
+                   double first_read_bytes, const uint64_t *array_in) {
     const PassDesc pd = make_passes(bit_lo, bit_hi);
     if (pd.passes > kMaxPasses) throw Error(-1, "sort bit range needs more than 8 passes");
     unsigned long long *hist = w.hist.as<unsigned long long>();
@@ -343,11 +347,37 @@ uint64_t *run_sort(const Src &first_src, uint64_t count, uint64_t *buf0, uint64_
     CG_HIP(hipGetLastError());
     if (w.prof) w.prof->end(K_SCAN, 0, 0);
 
+    // A pass whose digit is the same for every key is the identity: for
+    // large sorts the histograms come back to the host and such passes are
+    // skipped (for example the unused high nibbles of short states in a
+    // batched group).
+    int keep[kMaxPasses];
+    int nkeep = 0;
+    if (count >= kSkipCheckMin) {
+        unsigned long long h[kMaxPasses * kRadix];
+        CG_HIP(hipMemcpyAsync(h, hist, sizeof(unsigned long long) * kRadix * pd.passes, hipMemcpyDeviceToHost,
+                              w.stream));
+        CG_HIP(hipStreamSynchronize(w.stream));
+        for (int p = 0; p < pd.passes; ++p) {
+            bool trivial = false;
+            for (int d = 0; d < kRadix; ++d) trivial = trivial || h[p * kRadix + d] == count;
+            if (!trivial) keep[nkeep++] = p;
+        }
+    } else {
+        for (int p = 0; p < pd.passes; ++p) keep[nkeep++] = p;
+    }
+    if (nkeep == 0) {
+        if (!fused_first) return const_cast<uint64_t *>(array_in);
+        first_src.materialize(buf0, w);  // contiguous, generator-major
+        return buf0;
+    }
+
     uint64_t *cur_out = buf0;
     const uint64_t *cur_in = nullptr;
-    for (int p = 0; p < pd.passes; ++p) {
-        if (p == 0) {
-            const uint32_t epoch = w.next_epoch();
+    for (int q = 0; q < nkeep; ++q) {
+        const int p = keep[q];
+        const uint32_t epoch = w.next_epoch();
+        if (q == 0) {
             const int kind = fused_first ? K_SORT_FUSED : K_SORT;
             if (w.prof) w.prof->begin(kind);
             hipLaunchKernelGGL(onesweep_kernel<Src>, dim3(t0), dim3(kBlock), 0, w.stream, first_src,
@@ -356,7 +386,6 @@ uint64_t *run_sort(const Src &first_src, uint64_t count, uint64_t *buf0, uint64_
             CG_HIP(hipGetLastError());
             if (w.prof) w.prof->end(kind, first_read_bytes + 8.0 * (double)count, (double)count);
         } else {
-            const uint32_t epoch = w.next_epoch();
             const ArraySrc s{cur_in, count};
             if (w.prof) w.prof->begin(K_SORT);
             hipLaunchKernelGGL(onesweep_kernel<ArraySrc>, dim3(s.tiles()), dim3(kBlock), 0, w.stream,
@@ -389,7 +418,7 @@ uint64_t *radix_sort(uint64_t *keys, uint64_t *tmp, uint64_t count, int bit_lo, 
     w.ensure_status(sort_status_words(count));
     const ArraySrc src{keys, count};
     // pass 0 reads `keys` and writes `tmp`; then they alternate
-    return run_sort(src, count, tmp, keys, bit_lo, bit_hi, w, false, 8.0 * (double)count);
+    return run_sort(src, count, tmp, keys, bit_lo, bit_hi, w, false, 8.0 * (double)count, keys);
 }
 
 uint64_t *expand_sort(const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,
@@ -402,7 +431,7 @@ uint64_t *expand_sort(const uint64_t *frontier, uint64_t F, const GenSel *d_gsel
     }
     w.ensure_status(expand_sort_status_words(F, k));
     const ExpandSrc src{frontier, F, d_gsel, (uint32_t)k};
-    return run_sort(src, C, buf0, buf1, bit_lo, bit_hi, w, true, 8.0 * (double)F);
+    return run_sort(src, C, buf0, buf1, bit_lo, bit_hi, w, true, 8.0 * (double)F, nullptr);
 }
 
 }  // namespace cg

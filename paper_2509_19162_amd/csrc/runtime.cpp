@@ -1,7 +1,12 @@
 // Host runtime pieces: HIP error mapping, device buffers, look-back epochs,
 // HIP-event kernel profiling.
+#include <algorithm>
 #include <cstdio>
+#include <cstdlib>
+#include <iterator>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "../../include/cayleygrowth.h"
 #include "internal.h"
@@ -15,25 +20,213 @@ void hip_check(hipError_t e, const char *what, const char *file, int line) {
     throw Error(e == hipErrorOutOfMemory ? CG_E_NOMEM : CG_E_DEVICE, buf);
 }
 
+// ---------------------------------------------------------------------------
+// Device arena. On this driver a hipMalloc is fast while little memory is
+// held, but a large one takes seconds once tens of GB are already held. So
+// the first large request reserves one big region (CG_ARENA_FRACTION of the
+// free memory, default 0.85; 0 disables it) and every buffer is carved out
+// of it: best fit, split on allocation, coalesced on free. A freed range
+// carries an event recorded on its owner's stream and is reused only once
+// the event has completed, so work still queued on the old stream never
+// races with a new owner. Requests the arena cannot hold fall back to plain
+// hipMalloc/hipFree.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kAlign = 1u << 16;
+constexpr size_t kArenaMinRequest = 64u << 20;  // smaller buffers also use it once it exists
+
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0;
+    bool tried = false;
+    std::map<size_t, size_t> by_off;            // free ranges: offset -> length
+    std::multimap<size_t, size_t> by_len;       // free ranges: length -> offset
+    struct Pending {
+        size_t off, len;
+        hipEvent_t ev;
+    };
+    std::vector<Pending> pending;
+    size_t used = 0;
+
+    void insert_free(size_t off, size_t len) {
+        auto nx = by_off.lower_bound(off);
+        if (nx != by_off.end() && off + len == nx->first) {  // merge with the next range
+            erase_len(nx->second, nx->first);
+            len += nx->second;
+            nx = by_off.erase(nx);
+        }
+        if (nx != by_off.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) {  // merge with the previous range
+                erase_len(pv->second, pv->first);
+                off = pv->first;
+                len += pv->second;
+                by_off.erase(pv);
+            }
+        }
+        by_off[off] = len;
+        by_len.emplace(len, off);
+    }
+    void erase_len(size_t len, size_t off) {
+        auto r = by_len.equal_range(len);
+        for (auto it = r.first; it != r.second; ++it)
+            if (it->second == off) {
+                by_len.erase(it);
+                return;
+            }
+    }
+    void reclaim(bool wait) {
+        std::vector<Pending> keep;
+        for (auto &p : pending) {
+            bool done = true;
+            if (p.ev) {
+                if (wait) {
+                    (void)hipEventSynchronize(p.ev);
+                } else {
+                    const hipError_t q = hipEventQuery(p.ev);
+                    if (q == hipErrorNotReady) {
+                        done = false;
+                    } else if (q != hipSuccess) {
+                        (void)hipGetLastError();
+                        (void)hipEventSynchronize(p.ev);
+                    }
+                }
+            }
+            if (done) {
+                if (p.ev) (void)hipEventDestroy(p.ev);
+                insert_free(p.off, p.len);
+            } else {
+                keep.push_back(p);
+            }
+        }
+        pending.swap(keep);
+    }
+    bool take(size_t len, size_t &off) {
+        for (int pass = 0; pass < 2; ++pass) {
+            reclaim(pass == 1);
+            auto it = by_len.lower_bound(len);
+            if (it != by_len.end()) {
+                const size_t flen = it->first, foff = it->second;
+                by_len.erase(it);
+                by_off.erase(foff);
+                if (flen > len) insert_free(foff + len, flen - len);
+                off = foff;
+                used += len;
+                return true;
+            }
+            if (pending.empty()) break;
+        }
+        return false;
+    }
+};
+
+struct DeviceArenas {
+    std::mutex mu;
+    std::map<int, Arena> arena;
+};
+
+DeviceArenas &arenas() {
+    static DeviceArenas *a = new DeviceArenas();  // never destroyed: outlives every user
+    return *a;
+}
+
+int current_device() {
+    int d = 0;
+    (void)hipGetDevice(&d);
+    return d;
+}
+
+double arena_fraction() {
+    const char *e = std::getenv("CG_ARENA_FRACTION");
+    if (!e) return 0.85;
+    const double f = std::atof(e);
+    return f < 0 ? 0 : (f > 0.95 ? 0.95 : f);
+}
+
+// Returns a pointer inside the device's arena, or nullptr.
+void *arena_alloc(int dev, size_t len) {
+    std::lock_guard<std::mutex> lk(arenas().mu);
+    Arena &A = arenas().arena[dev];
+    if (!A.base) {
+        if (A.tried || len < kArenaMinRequest) return nullptr;
+        A.tried = true;
+        const double frac = arena_fraction();
+        size_t free_b = 0, total_b = 0;
+        if (frac <= 0 || hipMemGetInfo(&free_b, &total_b) != hipSuccess) return nullptr;
+        size_t want = (size_t)((double)free_b * frac) / kAlign * kAlign;
+        void *p = nullptr;
+        if (want < len || hipMalloc(&p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        A.base = (char *)p;
+        A.size = want;
+        A.insert_free(0, want);
+    }
+    size_t off = 0;
+    if (!A.take(len, off)) return nullptr;
+    return A.base + off;
+}
+
+bool arena_free(int dev, void *p, size_t len, hipEvent_t ev) {
+    std::lock_guard<std::mutex> lk(arenas().mu);
+    auto it = arenas().arena.find(dev);
+    if (it == arenas().arena.end() || !it->second.base) return false;
+    Arena &A = it->second;
+    char *c = (char *)p;
+    if (c < A.base || c >= A.base + A.size) return false;
+    A.pending.push_back({(size_t)(c - A.base), len, ev});
+    A.used -= len;
+    return true;
+}
+
+}  // namespace
+
+void release_cached_device_memory() {
+    std::lock_guard<std::mutex> lk(arenas().mu);
+    for (auto &kv : arenas().arena) {
+        Arena &A = kv.second;
+        if (!A.base || A.used) continue;  // ranges still handed out
+        A.reclaim(true);
+        (void)hipFree(A.base);
+        A = Arena{};
+    }
+}
+
+bool arena_active() {
+    const int dev = current_device();
+    std::lock_guard<std::mutex> lk(arenas().mu);
+    auto it = arenas().arena.find(dev);
+    return it != arenas().arena.end() && it->second.base;
+}
+
 bool DevBuf::ensure(size_t need, double slack) {
     if (need <= bytes && p) return false;
+    const size_t old = bytes;
     release();
     size_t want = (size_t)((double)need * slack);
     if (want < need) want = need;
-    if (want < 256) want = 256;
-    void *q = nullptr;
-    hipError_t e = hipMalloc(&q, want);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        if (want > need) {  // retry without slack
-            want = need;
-            e = hipMalloc(&q, want);
-        }
+    if (old && want < old + old / 2) want = std::max(need, old + old / 2);  // grow geometrically
+    if (arena_active()) want = need;  // re-carving the arena is cheap: no slack
+    want = (std::max<size_t>(want, 256) + kAlign - 1) / kAlign * kAlign;
+    dev = current_device();
+    void *q = arena_alloc(dev, want);
+    if (q) {
+        in_arena = true;
+    } else {
+        in_arena = false;
+        hipError_t e = hipMalloc(&q, want);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            char buf[160];
-            std::snprintf(buf, sizeof buf, "hipMalloc of %zu bytes failed", want);
-            throw Error(CG_E_NOMEM, buf);
+            want = (need + kAlign - 1) / kAlign * kAlign;  // retry without slack
+            e = hipMalloc(&q, want);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                char buf[160];
+                std::snprintf(buf, sizeof buf, "device allocation of %zu bytes failed", want);
+                throw Error(CG_E_NOMEM, buf);
+            }
         }
     }
     p = q;
@@ -42,13 +235,33 @@ bool DevBuf::ensure(size_t need, double slack) {
 }
 
 void DevBuf::release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+        if (in_arena) {
+            hipEvent_t ev = nullptr;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+                if (hipEventRecord(ev, stream) != hipSuccess) {
+                    (void)hipGetLastError();
+                    (void)hipEventDestroy(ev);
+                    ev = nullptr;
+                    (void)hipDeviceSynchronize();
+                }
+            } else {
+                (void)hipGetLastError();
+                ev = nullptr;
+                (void)hipDeviceSynchronize();
+            }
+            if (!arena_free(dev, p, bytes, ev) && ev) (void)hipEventDestroy(ev);
+        } else {
+            (void)hipFree(p);  // synchronises the device
+        }
+    }
     p = nullptr;
     bytes = 0;
 }
 
 void PipeWork::init(hipStream_t s) {
     stream = s;
+    for (DevBuf *b : {&hist, &base, &small, &status, &bounds, &tile_cnt, &tile_off}) b->stream = s;
     hist.ensure(kMaxPasses * 256 * sizeof(uint64_t));
     base.ensure(kMaxPasses * 256 * sizeof(uint64_t));
     small.ensure(32 * sizeof(uint32_t) + 4 * sizeof(uint32_t) + 8 * sizeof(uint64_t) + 256);
