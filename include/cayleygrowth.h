@@ -198,10 +198,11 @@ int cg_growth_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results,
 typedef struct cg_queue cg_queue_t;
 
 /*
- * Jobs with n <= 13 share one group of job-tagged keys (continuous
- * batching: they join and leave at super-step boundaries). Jobs with
- * n > 13, or whose estimated footprint exceeds a quarter of the budget,
- * run one at a time on a second lane with its own stream.
+ * Jobs with n <= 13 and orbits up to 2^21 states share one group of
+ * job-tagged keys (continuous batching: they join and leave at super-step
+ * boundaries). Larger jobs run on separate lanes (a thread, an engine and
+ * a stream each), concurrently with the group, admitted while their
+ * estimated footprint fits the budget.
  *   hbm_budget_bytes  device bytes the active jobs may use together
  *                     (0 = 60% of free memory at creation)
  *   max_active        most jobs on the device at once (0 = 256)
@@ -211,6 +212,7 @@ typedef struct cg_queue_opts {
     uint64_t hbm_budget_bytes;
     int max_active;
     int max_queued;
+    int large_lanes;  /* lanes for large jobs (0 = 2, at most 8)            */
 } cg_queue_opts_t;
 
 /* Creates the queue and its engine thread; NULL on failure (cg_last_error). */

@@ -89,6 +89,7 @@ class CgQueueOpts(ctypes.Structure):
         ("hbm_budget_bytes", ctypes.c_uint64),
         ("max_active", ctypes.c_int),
         ("max_queued", ctypes.c_int),
+        ("large_lanes", ctypes.c_int),
     ]
 
 

@@ -8,7 +8,9 @@ stream (``stream=torch.cuda.current_stream()``) when the caller wants one.
 
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional, Sequence
 
@@ -212,15 +214,35 @@ def growth_batch(jobs, max_layers: int = 256, max_active: int = 0, budget_bytes:
     return out
 
 
-class GrowthQueue:
-    """Request queue with continuous batching (``cg_queue_*``)."""
+_LIVE_QUEUES: "weakref.WeakSet[GrowthQueue]" = weakref.WeakSet()
 
-    def __init__(self, budget_bytes: int = 0, max_active: int = 0, max_queued: int = 0):
-        opts = N.CgQueueOpts(budget_bytes, max_active, max_queued)
+
+@atexit.register
+def _close_live_queues():
+    # a queue's engine threads must stop before the interpreter and the HIP
+    # runtime shut down, even if the caller never closed it
+    for q in list(_LIVE_QUEUES):
+        q.close()
+
+
+class GrowthQueue:
+    """Request queue with continuous batching (``cg_queue_*``). Use as a
+    context manager or call ``close()``; open queues are closed at exit."""
+
+    def __init__(self, budget_bytes: int = 0, max_active: int = 0, max_queued: int = 0,
+                 large_lanes: int = 0):
+        opts = N.CgQueueOpts(budget_bytes, max_active, max_queued, large_lanes)
         self._q = N.lib().cg_queue_create(ctypes.byref(opts))
         if not self._q:
             raise CGError(N.CG_E_DEVICE, N.lib().cg_last_error().decode())
         self._jobs: Dict[int, _JobHolder] = {}
+        _LIVE_QUEUES.add(self)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def submit(self, n: int, gens, max_layers: int = 256, max_frontier: Optional[int] = None) -> int:
         h = _JobHolder(n, gens, max_layers, max_frontier, 0, None, 0)

@@ -131,8 +131,7 @@ void BatchGroup::step(std::vector<int> &finished) {
                               stream_));
         merged_.ensure((ncur_ + np) * sizeof(uint64_t), 1.5);
         launch_merge(lay_[ic_].as<uint64_t>(), ncur_, join_.as<uint64_t>(), np, merged_.as<uint64_t>(), stream_);
-        std::swap(lay_[ic_].p, merged_.p);
-        std::swap(lay_[ic_].bytes, merged_.bytes);
+        lay_[ic_].swap(merged_);
         ncur_ += np;
         for (auto &J : slot_)
             if (J.res && J.F == 0 && J.layers == 1 && !J.done) J.F = 1;

@@ -261,8 +261,7 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
                 CG_HIP(hipMemcpyAsync(bigger.p, arena_.p, total * sizeof(uint64_t),
                                       hipMemcpyDeviceToDevice, stream_));
                 CG_HIP(hipStreamSynchronize(stream_));
-                std::swap(arena_.p, bigger.p);
-                std::swap(arena_.bytes, bigger.bytes);
+                arena_.swap(bigger);
             }
             const uint64_t d = off.size() - 2;  // index of L_d
             Ld = arena_.as<uint64_t>() + off[d];

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace cg {
@@ -95,6 +96,17 @@ struct DevBuf {
     // the buffer was reallocated. Memory comes from the device arena.
     bool ensure(size_t need, double slack = 1.0);
     void release();
+    // Exchanges the memory of two buffers (with where it came from; the
+    // streams stay with their owners).
+    void swap(DevBuf &o) {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+        std::swap(dev, o.dev);
+        std::swap(in_arena, o.in_arena);
+    }
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
     template <class T>
     T *as() const { return static_cast<T *>(p); }

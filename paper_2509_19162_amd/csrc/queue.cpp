@@ -5,9 +5,10 @@
 // free slots of a shared group (job-tagged keys, see batch_kernels.hip) at
 // a super-step boundary, runs one super-step for every admitted job, and
 // retires finished jobs (result written, timestamps set, waiters woken).
-// Jobs too large to share a group (n > 13, or an estimate above a quarter
-// of the budget) run one at a time on a second lane with its own stream, so
-// they do not stall the small jobs.
+// Large jobs (n > 13, an orbit above 2^21 states, or an estimate above a
+// quarter of the budget) run on separate lanes, each a thread with its own
+// engine and stream, so their work overlaps with the shared group's on the
+// device and they do not hold back the small jobs' super-steps.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -26,6 +27,7 @@ namespace cg {
 namespace {
 
 constexpr int kSharedN = 13;  // 4*13 state bits + 12 tag bits = 64
+constexpr uint64_t kLargeOrbit = 1ull << 21;
 
 // Upper estimate of a job's peak device bytes: the largest layer is taken
 // as 35% of the orbit (capped by what the stop rules allow), times the
@@ -58,7 +60,9 @@ struct cg_queue {
     cg_queue_opts_t opts{};
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::thread engine, big_lane;
+    std::thread engine;
+    std::vector<std::thread> big_lanes;
+    int big_running = 0;
     bool stopping = false;
     uint64_t next_ticket = 1;
     uint64_t budget = 0, in_use = 0;
@@ -156,17 +160,25 @@ void cg_queue::big_loop() {
         cg::QueueReq *r = nullptr;
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv_work.wait(lk, [&] { return stopping || !big_queued.empty(); });
+            // admission: a large job starts when the budget allows it or no
+            // other large job runs
+            cv_work.wait(lk, [&] {
+                return stopping || (!big_queued.empty() &&
+                                    (big_running == 0 || in_use + big_queued.front()->bytes <= budget));
+            });
             if (big_queued.empty()) break;
             r = big_queued.front();
             big_queued.pop_front();
             if (r->cancel || stopping) {
                 r->res->t_submit = r->t_submit;
                 r->res->t_admit = r->res->t_done = cg::now_seconds();
+                r->bytes = 0;
                 retire(r, CG_E_CANCELLED);
                 continue;
             }
             r->state = 1;
+            in_use += r->bytes;
+            ++big_running;
         }
         const double t_admit = cg::now_seconds();
         int status;
@@ -183,7 +195,9 @@ void cg_queue::big_loop() {
         r->res->t_submit = r->t_submit;
         r->res->t_admit = t_admit;
         r->res->t_done = cg::now_seconds();
+        --big_running;
         retire(r, status);
+        cv_work.notify_all();  // budget freed: other large jobs may start
     }
 }
 
@@ -197,7 +211,8 @@ cg_queue_t *cg_queue_create(const cg_queue_opts_t *opts) {
         CG_HIP(hipMemGetInfo(&free_b, &total_b));
         q->budget = q->opts.hbm_budget_bytes ? q->opts.hbm_budget_bytes : (uint64_t)(0.6 * (double)free_b);
         q->engine = std::thread([p = q.get()] { p->engine_loop(); });
-        q->big_lane = std::thread([p = q.get()] { p->big_loop(); });
+        const int lanes = q->opts.large_lanes > 0 ? std::min(q->opts.large_lanes, 8) : 2;
+        for (int i = 0; i < lanes; ++i) q->big_lanes.emplace_back([p = q.get()] { p->big_loop(); });
         return q.release();
     } catch (const std::exception &e) {
         cg::set_last_error(e.what());
@@ -223,12 +238,11 @@ int cg_queue_submit(cg_queue_t *q, const cg_job_t *job, cg_result_t *res_slot, u
     const int max_q = q->opts.max_queued > 0 ? q->opts.max_queued : 65536;
     if ((int)(q->queued.size() + q->big_queued.size()) >= max_q) return CG_E_BUSY;
     r->ticket = q->next_ticket++;
-    r->big = r->spec.n > cg::kSharedN || r->bytes > q->budget / 4;
+    r->big = r->spec.n > cg::kSharedN || r->spec.orbit_bound > cg::kLargeOrbit || r->bytes > q->budget / 4;
     *ticket = r->ticket;
     cg::QueueReq *p = r.get();
     q->reqs[r->ticket] = std::move(r);
     if (p->big) {
-        p->bytes = 0;  // the big lane runs alone; its memory is not shared
         q->big_queued.push_back(p);
     } else {
         q->queued.push_back(p);
@@ -280,7 +294,8 @@ void cg_queue_destroy(cg_queue_t *q) {
         q->cv_work.notify_all();
     }
     if (q->engine.joinable()) q->engine.join();
-    if (q->big_lane.joinable()) q->big_lane.join();
+    for (auto &t : q->big_lanes)
+        if (t.joinable()) t.join();
     delete q;
 }
 

@@ -252,7 +252,7 @@ void DevBuf::release() {
             }
             if (!arena_free(dev, p, bytes, ev) && ev) (void)hipEventDestroy(ev);
         } else {
-            (void)hipFree(p);  // synchronises the device
+            (void)hipFree(p);  // a block of its own; synchronises the device
         }
     }
     p = nullptr;

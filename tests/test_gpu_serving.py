@@ -14,7 +14,11 @@ from paper_2509_19162_amd import inputs as I  # noqa: E402
 
 def test_queue_results_equal_alone_under_concurrent_submitters(oracle_c):
     reqs = [I.serving_request(i, n_lo=5, n_hi=9) for i in range(120)]
-    q = api.GrowthQueue(max_active=32)
+    with api.GrowthQueue(max_active=32) as q:
+        _submit_and_check(q, reqs, oracle_c)
+
+
+def _submit_and_check(q, reqs, oracle_c):
     tickets = [None] * len(reqs)
 
     def submit(lo, hi):
@@ -32,24 +36,26 @@ def test_queue_results_equal_alone_under_concurrent_submitters(oracle_c):
         exp, rc, _ = oracle_c.growth(n, gens, max_layers=512)
         assert r.sizes == exp and r.status == rc, (i, n, fam)
         assert r.t_submit <= r.t_admit <= r.t_done
-    q.close()
 
 
 def test_queue_stop_rules_and_big_lane(oracle_c):
-    # a small budget sends the larger jobs to the one-at-a-time lane
-    q = api.GrowthQueue(budget_bytes=64 << 20, max_active=8)
-    jobs = [(9, I.pancake(9), None), (10, I.lrx(10), 500), (7, I.coxeter(7), None),
-            (10, I.star(10), None), (6, I.all_transpositions(6), None)]
-    ts = [q.submit(n, g, max_layers=512, max_frontier=mf) for n, g, mf in jobs]
-    for (n, g, mf), t in zip(jobs, ts):
-        r = q.wait(t, timeout_s=120)
-        exp, rc, _ = oracle_c.growth(n, g, max_layers=512, max_frontier=mf or 0)
-        assert r.sizes == exp and r.status == rc
-    q.close()
+    # a small budget and large orbits send jobs to the large-job lanes
+    with api.GrowthQueue(budget_bytes=64 << 20, max_active=8) as q:
+        jobs = [(9, I.pancake(9), None), (10, I.lrx(10), 500), (7, I.coxeter(7), None),
+                (10, I.star(10), None), (6, I.all_transpositions(6), None), (11, I.coxeter(11), None)]
+        ts = [q.submit(n, g, max_layers=512, max_frontier=mf) for n, g, mf in jobs]
+        for (n, g, mf), t in zip(jobs, ts):
+            r = q.wait(t, timeout_s=120)
+            exp, rc, _ = oracle_c.growth(n, g, max_layers=512, max_frontier=mf or 0)
+            assert r.sizes == exp and r.status == rc
 
 
 def test_queue_cancel_and_poll():
-    q = api.GrowthQueue(max_active=4)
+    with api.GrowthQueue(max_active=4) as q:
+        _cancel_and_poll(q)
+
+
+def _cancel_and_poll(q):
     t_big = q.submit(11, I.all_transpositions(11))
     t_small = q.submit(5, I.coxeter(5))
     assert q.cancel(t_big) == N.CG_OK
@@ -62,11 +68,9 @@ def test_queue_cancel_and_poll():
     rc = N.lib().cg_queue_wait(q._q, t_big, 60_000_000)
     assert rc in (N.CG_E_CANCELLED, N.CG_OK)
     assert N.lib().cg_queue_poll(q._q, 987654) == N.CG_E_INVAL
-    q.close()
 
 
 def test_queue_rejects_invalid_job():
-    q = api.GrowthQueue()
-    with pytest.raises(api.CGError):
-        q.submit(4, [[0, 1, 1, 2]])
-    q.close()
+    with api.GrowthQueue() as q:
+        with pytest.raises(api.CGError):
+            q.submit(4, [[0, 1, 1, 2]])
