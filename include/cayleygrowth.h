@@ -66,6 +66,9 @@ extern "C" {
                                     vector with repeated entries)            */
 #define CG_PROFILE 0x8u          /* record per-kernel HIP-event timings into
                                     cg_result_t.kstats                        */
+#define CG_PACKED_SORT 0x10u     /* sort candidates as packed 64-bit keys
+                                    even when n <= 12 (by default they sort
+                                    as 32-bit lexicographic ranks there)     */
 
 /*
  * A growth job.

@@ -74,6 +74,25 @@ int cg_test_layer_step(int n, const uint8_t *h_gens, int k,
                        const uint64_t *d_prev, uint64_t np, uint64_t *d_out,
                        uint64_t *h_count, void *stream);
 
+/*
+ * Lexicographic rank of permutation keys (n <= 12): h_ranks[i] = the index
+ * of the permutation in lexicographic order of S_n. on_device = 1 runs the
+ * device code (host buffers are staged), 0 the same code on the host.
+ * cg_test_unrank is the inverse (h_ranks < n! required).
+ */
+int cg_test_rank(int n, const uint64_t *h_keys, uint64_t count, uint32_t *h_ranks,
+                 int on_device, void *stream);
+int cg_test_unrank(int n, const uint32_t *h_ranks, uint64_t count, uint64_t *h_keys,
+                   int on_device, void *stream);
+
+/*
+ * Host emulation of the byte-permute expand (v_perm_b32 semantics written
+ * out on the CPU): h_out[g*F + f] = key(s_f . g). Checks the selector
+ * tables without a GPU.
+ */
+int cg_test_host_expand(int n, const uint8_t *h_gens, int k, const uint64_t *h_frontier,
+                        uint64_t F, uint64_t *h_out);
+
 #ifdef __cplusplus
 }
 #endif

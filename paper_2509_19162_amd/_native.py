@@ -28,6 +28,7 @@ CG_KEEP_ALL_LAYERS = 0x1
 CG_ALLOW_DIRECTED = 0x2
 CG_START_STATE = 0x4
 CG_PROFILE = 0x8
+CG_PACKED_SORT = 0x10
 
 CG_KSTAT_MAX = 8
 
@@ -121,6 +122,11 @@ SIGNATURES = [
     ("cg_test_dedup", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
       ctypes.c_uint64, ctypes.c_void_p, u64p, ctypes.c_void_p]),
+    ("cg_test_rank", ctypes.c_int,
+     [ctypes.c_int, u64p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int, ctypes.c_void_p]),
+    ("cg_test_unrank", ctypes.c_int,
+     [ctypes.c_int, ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint64, u64p, ctypes.c_int, ctypes.c_void_p]),
+    ("cg_test_host_expand", ctypes.c_int, [ctypes.c_int, u8p, ctypes.c_int, u64p, ctypes.c_uint64, u64p]),
     ("cg_test_layer_step", ctypes.c_int,
      [ctypes.c_int, u8p, ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
       ctypes.c_uint64, ctypes.c_void_p, u64p, ctypes.c_void_p]),

@@ -136,7 +136,7 @@ def growth(n: int, gens: Sequence[Sequence[int]], max_layers: int = 256,
 def growth_ex(n: int, gens: Sequence[Sequence[int]], max_layers: int = 256,
               max_frontier: Optional[int] = None, start: Optional[Sequence[int]] = None,
               keep_all_layers: bool = False, allow_directed: bool = False, profile: bool = False,
-              export_layers: int = 0, stream=None) -> GrowthResult:
+              export_layers: int = 0, stream=None, packed_sort: bool = False) -> GrowthResult:
     """The full job interface (``cg_growth_ex``).
 
     ``export_layers``: capacity (in states) of the layer-content export; the
@@ -150,6 +150,8 @@ def growth_ex(n: int, gens: Sequence[Sequence[int]], max_layers: int = 256,
         flags |= N.CG_ALLOW_DIRECTED
     if profile:
         flags |= N.CG_PROFILE
+    if packed_sort:
+        flags |= N.CG_PACKED_SORT
     h = _JobHolder(n, gens, max_layers, max_frontier, flags, start, export_layers)
     _check(N.lib().cg_growth_ex(ctypes.byref(h.job), ctypes.byref(h.res), _stream_handle(stream)))
     return h.result()
@@ -166,9 +168,10 @@ class Engine:
 
     def run(self, n: int, gens, max_layers: int = 256, max_frontier: Optional[int] = None,
             start=None, keep_all_layers: bool = False, allow_directed: bool = False,
-            profile: bool = False, export_layers: int = 0) -> GrowthResult:
+            profile: bool = False, export_layers: int = 0, packed_sort: bool = False) -> GrowthResult:
         flags = (N.CG_KEEP_ALL_LAYERS if keep_all_layers else 0) | \
-                (N.CG_ALLOW_DIRECTED if allow_directed else 0) | (N.CG_PROFILE if profile else 0)
+                (N.CG_ALLOW_DIRECTED if allow_directed else 0) | (N.CG_PROFILE if profile else 0) | \
+                (N.CG_PACKED_SORT if packed_sort else 0)
         h = _JobHolder(n, gens, max_layers, max_frontier, flags, start, export_layers)
         _check(N.lib().cg_engine_run(self._e, ctypes.byref(h.job), ctypes.byref(h.res)))
         return h.result()

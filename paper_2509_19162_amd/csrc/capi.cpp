@@ -11,6 +11,7 @@
 #include "../../include/cayleygrowth_testing.h"
 #include "batch.h"
 #include "engine.h"
+#include "perm_rank.h"
 
 namespace {
 
@@ -272,6 +273,118 @@ int cg_test_layer_step(int n, const uint8_t *h_gens, int k, const uint64_t *d_fr
         CG_HIP(hipStreamSynchronize(s));
         if (err) throw cg::Error(CG_E_DEVICE, "kernel error flag set (look-back bound or offset check)");
         *h_count = cnt;
+        return CG_OK;
+    });
+}
+
+// ---- rank / unrank / host expand -------------------------------------------------
+
+namespace {
+
+__global__ void rank_kernel(int n, const uint64_t *k, uint64_t count, uint32_t *r) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) r[i] = cg::perm_rank(k[i], n);
+}
+
+__global__ void unrank_kernel(int n, const uint32_t *r, uint64_t count, uint64_t *k) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) k[i] = cg::perm_unrank(r[i], n);
+}
+
+// v_perm_b32: byte j of the result selects from the 8-byte {s0:s1} (s1 the
+// low dword); selector 0x0C gives zero.
+uint32_t vperm_host(uint32_t s0, uint32_t s1, uint32_t sel) {
+    const uint64_t src = ((uint64_t)s0 << 32) | s1;
+    uint32_t out = 0;
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t b = (sel >> (8 * j)) & 0xFF;
+        uint32_t v = 0;
+        if (b < 8)
+            v = (uint32_t)((src >> (8 * b)) & 0xFF);
+        else if (b == 12)
+            v = 0;
+        else
+            v = b >= 13 ? 0xFF : 0;  // sign replication forms are never produced
+        out |= v << (8 * j);
+    }
+    return out;
+}
+
+}  // namespace
+
+int cg_test_rank(int n, const uint64_t *h_keys, uint64_t count, uint32_t *h_ranks, int on_device,
+                 void *stream) {
+    return guarded([&]() -> int {
+        if (n < 1 || n > cg::kRankMaxN || (count && (!h_keys || !h_ranks)))
+            throw cg::Error(CG_E_INVAL, "bad rank arguments");
+        if (!on_device) {
+            for (uint64_t i = 0; i < count; ++i) h_ranks[i] = cg::perm_rank(h_keys[i], n);
+            return CG_OK;
+        }
+        if (!count) return CG_OK;
+        hipStream_t s = (hipStream_t)stream;
+        cg::DevBuf a, b;
+        a.stream = b.stream = s;
+        a.ensure(count * 8);
+        b.ensure(count * 4);
+        CG_HIP(hipMemcpyAsync(a.p, h_keys, count * 8, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(rank_kernel, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, s, n,
+                           a.as<uint64_t>(), count, b.as<uint32_t>());
+        CG_HIP(hipGetLastError());
+        CG_HIP(hipMemcpyAsync(h_ranks, b.p, count * 4, hipMemcpyDeviceToHost, s));
+        CG_HIP(hipStreamSynchronize(s));
+        return CG_OK;
+    });
+}
+
+int cg_test_unrank(int n, const uint32_t *h_ranks, uint64_t count, uint64_t *h_keys, int on_device,
+                   void *stream) {
+    return guarded([&]() -> int {
+        if (n < 1 || n > cg::kRankMaxN || (count && (!h_keys || !h_ranks)))
+            throw cg::Error(CG_E_INVAL, "bad unrank arguments");
+        uint64_t fact = 1;
+        for (int i = 2; i <= n; ++i) fact *= (uint64_t)i;
+        for (uint64_t i = 0; i < count; ++i)
+            if (h_ranks[i] >= fact) throw cg::Error(CG_E_INVAL, "rank out of range");
+        if (!on_device) {
+            for (uint64_t i = 0; i < count; ++i) h_keys[i] = cg::perm_unrank(h_ranks[i], n);
+            return CG_OK;
+        }
+        if (!count) return CG_OK;
+        hipStream_t s = (hipStream_t)stream;
+        cg::DevBuf a, b;
+        a.stream = b.stream = s;
+        a.ensure(count * 4);
+        b.ensure(count * 8);
+        CG_HIP(hipMemcpyAsync(a.p, h_ranks, count * 4, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(unrank_kernel, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, s, n,
+                           a.as<uint32_t>(), count, b.as<uint64_t>());
+        CG_HIP(hipGetLastError());
+        CG_HIP(hipMemcpyAsync(h_keys, b.p, count * 8, hipMemcpyDeviceToHost, s));
+        CG_HIP(hipStreamSynchronize(s));
+        return CG_OK;
+    });
+}
+
+int cg_test_host_expand(int n, const uint8_t *h_gens, int k, const uint64_t *h_frontier, uint64_t F,
+                        uint64_t *h_out) {
+    return guarded([&]() -> int {
+        auto sels = make_sels(n, h_gens, k);
+        if (F && (!h_frontier || !h_out)) throw cg::Error(CG_E_INVAL, "NULL pointer");
+        for (int g = 0; g < k; ++g) {
+            const cg::GenSel &sel = sels[g];
+            for (uint64_t f = 0; f < F; ++f) {
+                const uint64_t key = h_frontier[f];
+                const uint32_t lo = (uint32_t)key, hi = (uint32_t)(key >> 32);
+                const uint32_t e0 = lo & 0x0F0F0F0Fu, o0 = (lo >> 4) & 0x0F0F0F0Fu;
+                const uint32_t e1 = hi & 0x0F0F0F0Fu, o1 = (hi >> 4) & 0x0F0F0F0Fu;
+                const uint32_t ye0 = vperm_host(e1, e0, sel.sel[0]) | vperm_host(o1, o0, sel.sel[1]);
+                const uint32_t ye1 = vperm_host(e1, e0, sel.sel[2]) | vperm_host(o1, o0, sel.sel[3]);
+                const uint32_t yo0 = vperm_host(e1, e0, sel.sel[4]) | vperm_host(o1, o0, sel.sel[5]);
+                const uint32_t yo1 = vperm_host(e1, e0, sel.sel[6]) | vperm_host(o1, o0, sel.sel[7]);
+                h_out[(uint64_t)g * F + f] = ((uint64_t)(ye1 | (yo1 << 4)) << 32) | (ye0 | (yo0 << 4));
+            }
+        }
         return CG_OK;
     });
 }

@@ -24,6 +24,7 @@
 //     sorted and contiguous.
 #include "internal.h"
 #include "device_util.h"
+#include "perm_rank.h"
 
 namespace cg {
 
@@ -37,12 +38,30 @@ constexpr int kRef = 2048;            // reference keys per LDS chunk
 
 __device__ __forceinline__ uint32_t pad(uint32_t i) { return i + (i >> 4); }
 
+// Candidates are packed 64-bit keys, or (n <= 12) their 32-bit
+// lexicographic ranks. The policy turns a layer key into the candidates'
+// form and a candidate back into a layer key; both preserve order.
+struct PackedKeys {
+    using K = uint64_t;
+    int n;
+    __device__ __forceinline__ K from_layer(uint64_t x) const { return x; }
+    __device__ __forceinline__ uint64_t to_layer(K x) const { return x; }
+};
+struct RankedKeys {
+    using K = uint32_t;
+    int n;
+    __device__ __forceinline__ K from_layer(uint64_t x) const { return perm_rank(x, n); }
+    __device__ __forceinline__ uint64_t to_layer(K x) const { return perm_unrank(x, n); }
+};
+
 // bounds[4t + 0/1]: lower bound of tile t's first key / upper bound of its
 // last key in A; bounds[4t + 2/3]: the same in B. One thread per bound; the
 // searches of neighbouring tiles share their upper levels in the caches.
+template <class P>
 __global__ __launch_bounds__(256) void tile_bounds_kernel(
-    const uint64_t *__restrict__ S, uint64_t C, const uint64_t *__restrict__ A, uint64_t na,
+    P pol, const typename P::K *__restrict__ S, uint64_t C, const uint64_t *__restrict__ A, uint64_t na,
     const uint64_t *__restrict__ B, uint64_t nb, uint64_t *__restrict__ bounds, uint32_t ntiles) {
+    using K = typename P::K;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 4 * ntiles) return;
     const uint32_t t = i >> 2, w = i & 3u;
@@ -50,11 +69,11 @@ __global__ __launch_bounds__(256) void tile_bounds_kernel(
     const uint64_t nr = w < 2 ? na : nb;
     const bool upper = (w & 1u) != 0;
     const uint64_t end = ((uint64_t)t + 1) * kTile < C ? ((uint64_t)t + 1) * kTile : C;
-    const uint64_t key = upper ? S[end - 1] : S[(uint64_t)t * kTile];
+    const K key = upper ? S[end - 1] : S[(uint64_t)t * kTile];
     uint64_t lo = 0, hi = nr;
     while (lo < hi) {
         const uint64_t mid = (lo + hi) >> 1;
-        const uint64_t v = R[mid];
+        const K v = pol.from_layer(R[mid]);
         if (upper ? (v <= key) : (v < key))
             lo = mid + 1;
         else
@@ -66,12 +85,14 @@ __global__ __launch_bounds__(256) void tile_bounds_kernel(
 // Phase 1: one tile per block (no inter-tile dependency): unique + set
 // difference, survivors compacted within the tile into tmp[tile*kTile ..]
 // and counted in cnt[tile].
+template <class P>
 __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
-    const uint64_t *__restrict__ S, uint64_t C, const uint64_t *__restrict__ A, uint64_t na,
+    P pol, const typename P::K *__restrict__ S, uint64_t C, const uint64_t *__restrict__ A, uint64_t na,
     const uint64_t *__restrict__ B, uint64_t nb, const uint64_t *__restrict__ bounds,
-    uint64_t *__restrict__ tmp, uint32_t *__restrict__ cnt) {
-    __shared__ uint64_t s_keys[kTile + kTile / 16];
-    __shared__ uint64_t s_ref[kRef];
+    typename P::K *__restrict__ tmp, uint32_t *__restrict__ cnt) {
+    using K = typename P::K;
+    __shared__ K s_keys[kTile + kTile / 16];
+    __shared__ K s_ref[kRef];
     __shared__ uint32_t s_scan[kWaves];
 
     const uint32_t tid = threadIdx.x;
@@ -83,10 +104,10 @@ __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
 #pragma unroll
     for (int j = 0; j < kIpt; ++j) {
         const uint32_t i = j * kBlock + tid;
-        s_keys[pad(i)] = i < nvalid ? S[base + i] : kSentinel;
+        s_keys[pad(i)] = i < nvalid ? S[base + i] : (K)kSentinel;
     }
     const bool has_prev = base > 0;
-    const uint64_t prev_global = has_prev ? S[base - 1] : 0;
+    const K prev_global = has_prev ? S[base - 1] : (K)0;
     uint64_t bnd[4] = {0, 0, 0, 0};
     if (na) {
         bnd[0] = bounds[4 * (uint64_t)tile];
@@ -98,13 +119,13 @@ __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
     }
     __syncthreads();
 
-    uint64_t k[kIpt];
+    K k[kIpt];
     uint32_t keep = 0;
 #pragma unroll
     for (int j = 0; j < kIpt; ++j) {
         const uint32_t idx = tid * kIpt + j;
         k[j] = s_keys[pad(idx)];
-        uint64_t prev;
+        K prev;
         bool first;
         if (j > 0) {
             prev = k[j - 1];
@@ -125,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
         for (uint64_t c0 = lo; c0 < hi; c0 += kRef) {
             const uint64_t rem = hi - c0;
             const uint32_t m = (uint32_t)(rem < (uint64_t)kRef ? rem : (uint64_t)kRef);
-            for (uint32_t i = tid; i < m; i += kBlock) s_ref[i] = R[c0 + i];
+            for (uint32_t i = tid; i < m; i += kBlock) s_ref[i] = pol.from_layer(R[c0 + i]);
             __syncthreads();
             if (keep) {
                 // 16 independent branchless lower-bound searches, advanced
@@ -143,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
                 }
 #pragma unroll
                 for (int j = 0; j < kIpt; ++j) {
-                    const uint64_t v = s_ref[pos[j]];
+                    const K v = s_ref[pos[j]];
                     const uint32_t lb = pos[j] + (v < k[j] ? 1u : 0u);
                     if (lb < m && s_ref[lb] == k[j]) keep &= ~(1u << j);
                 }
@@ -217,7 +238,8 @@ __global__ __launch_bounds__(kScanBlock) void count_scan_kernel(
 }
 
 // Phase 3: move each tile's survivors to their final place.
-__global__ __launch_bounds__(kBlock) void gather_kernel(const uint64_t *__restrict__ tmp,
+template <class P>
+__global__ __launch_bounds__(kBlock) void gather_kernel(P pol, const typename P::K *__restrict__ tmp,
                                                         const uint32_t *__restrict__ cnt,
                                                         const uint64_t *__restrict__ off,
                                                         uint64_t *__restrict__ out, uint64_t out_cap,
@@ -228,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(const uint64_t *__restri
     const uint64_t base = (uint64_t)tile * kTile;
     for (uint32_t i = threadIdx.x; i < c; i += kBlock) {
         if (o + i < out_cap)
-            out[o + i] = tmp[base + i];
+            out[o + i] = pol.to_layer(tmp[base + i]);
         else
             atomicOr(err, 4u);  // more survivors than the output holds
     }
@@ -241,9 +263,11 @@ uint64_t dedup_status_words(uint64_t C) {
     return (tiles + kScanTile - 1) / kScanTile;
 }
 
-void launch_dedup_count(const uint64_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,
-                        const uint64_t *b, uint64_t nb, uint64_t *tmp, uint64_t *d_count,
-                        PipeWork &w) {
+namespace {
+
+template <class P>
+void dedup_count_impl(P pol, const typename P::K *sorted, uint64_t C, const uint64_t *a, uint64_t na,
+                      const uint64_t *b, uint64_t nb, typename P::K *tmp, uint64_t *d_count, PipeWork &w) {
     uint32_t *ticket = w.tickets() + 31;
     // clears the ticket and the output count (a kernel, not a memset, so the
     // sequence stays valid inside a captured graph)
@@ -259,12 +283,12 @@ void launch_dedup_count(const uint64_t *sorted, uint64_t C, const uint64_t *a, u
     const uint32_t epoch = w.next_epoch();
     if (w.prof) w.prof->begin(K_DEDUP);
     if (na || nb) {
-        hipLaunchKernelGGL(tile_bounds_kernel, dim3((4 * ntiles + 255) / 256), dim3(256), 0, w.stream,
-                           sorted, C, a, na, b, nb, w.bounds.as<uint64_t>(), ntiles);
+        hipLaunchKernelGGL(tile_bounds_kernel<P>, dim3((4 * ntiles + 255) / 256), dim3(256), 0, w.stream,
+                           pol, sorted, C, a, na, b, nb, w.bounds.as<uint64_t>(), ntiles);
         CG_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(dedup_local_kernel, dim3(ntiles), dim3(kBlock), 0, w.stream, sorted, C, a, na,
-                       b, nb, w.bounds.as<const uint64_t>(), tmp, w.tile_cnt.as<uint32_t>());
+    hipLaunchKernelGGL(dedup_local_kernel<P>, dim3(ntiles), dim3(kBlock), 0, w.stream, pol, sorted, C, a,
+                       na, b, nb, w.bounds.as<const uint64_t>(), tmp, w.tile_cnt.as<uint32_t>());
     CG_HIP(hipGetLastError());
     hipLaunchKernelGGL(count_scan_kernel, dim3(nscan), dim3(kScanBlock), 0, w.stream,
                        w.tile_cnt.as<const uint32_t>(), ntiles, w.tile_off.as<uint64_t>(), d_count,
@@ -273,18 +297,42 @@ void launch_dedup_count(const uint64_t *sorted, uint64_t C, const uint64_t *a, u
     // algorithmic traffic: candidates and both reference layers are read
     // once; the 8N bytes of the output are added by the caller once N is
     // known
-    if (w.prof) w.prof->end(K_DEDUP, 8.0 * (double)(C + na + nb), (double)C);
+    if (w.prof)
+        w.prof->end(K_DEDUP, (double)sizeof(typename P::K) * (double)C + 8.0 * (double)(na + nb), (double)C);
     w.dedup_tiles = ntiles;
 }
 
-void launch_dedup_gather(const uint64_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w) {
+template <class P>
+void dedup_gather_impl(P pol, const typename P::K *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w) {
     if (!w.dedup_tiles) return;
     if (w.prof) w.prof->begin(K_DEDUP);
-    hipLaunchKernelGGL(gather_kernel, dim3(w.dedup_tiles), dim3(kBlock), 0, w.stream, tmp,
+    hipLaunchKernelGGL(gather_kernel<P>, dim3(w.dedup_tiles), dim3(kBlock), 0, w.stream, pol, tmp,
                        w.tile_cnt.as<const uint32_t>(), w.tile_off.as<const uint64_t>(), out, out_cap,
                        w.err());
     CG_HIP(hipGetLastError());
     if (w.prof) w.prof->end(K_DEDUP, 0, 0);
+}
+
+}  // namespace
+
+void launch_dedup_count(const uint64_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,
+                        const uint64_t *b, uint64_t nb, uint64_t *tmp, uint64_t *d_count,
+                        PipeWork &w) {
+    dedup_count_impl(PackedKeys{0}, sorted, C, a, na, b, nb, tmp, d_count, w);
+}
+
+void launch_dedup_gather(const uint64_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w) {
+    dedup_gather_impl(PackedKeys{0}, tmp, out, out_cap, w);
+}
+
+void launch_dedup_count_ranked(int n, const uint32_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,
+                               const uint64_t *b, uint64_t nb, uint32_t *tmp, uint64_t *d_count,
+                               PipeWork &w) {
+    dedup_count_impl(RankedKeys{n}, sorted, C, a, na, b, nb, tmp, d_count, w);
+}
+
+void launch_dedup_gather_ranked(int n, const uint32_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w) {
+    dedup_gather_impl(RankedKeys{n}, tmp, out, out_cap, w);
 }
 
 void launch_dedup(const uint64_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,

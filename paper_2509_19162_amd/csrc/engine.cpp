@@ -13,6 +13,8 @@
 // after recording the first layer larger than max_frontier (truncated).
 #include "engine.h"
 
+#include "perm_rank.h"
+
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -226,6 +228,19 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
     export_layer(spec, keep_all ? arena_.as<uint64_t>() : lay_[1].as<uint64_t>(), 1, written);
 
     const int bit_lo = 4, bit_hi = 4 * n;
+    // Candidates sort as 32-bit lexicographic ranks when the states are
+    // permutations of 0..n-1 with n <= 12 (12! < 2^32); layers stay packed.
+    bool perm_start = n <= kRankMaxN;
+    {
+        bool seen[16] = {false};
+        for (int i = 0; i < n && perm_start; ++i) {
+            if (spec.start[i] >= n || seen[spec.start[i]]) perm_start = false;
+            else seen[spec.start[i]] = true;
+        }
+    }
+    const bool ranked = perm_start && !(spec.flags & CG_PACKED_SORT);
+    int rank_bits = 0;
+    while (rank_bits < 32 && (1ull << rank_bits) < spec.orbit_bound) ++rank_bits;
     int layers = 1;
     int status = CG_OK;
     for (;;) {
@@ -244,8 +259,9 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
         const uint64_t C = F * (uint64_t)k;
         const uint64_t room = spec.orbit_bound > total ? spec.orbit_bound - total : 0;
         const uint64_t out_cap = std::max<uint64_t>(1, std::min(C, room));
-        cand0_.ensure(C * sizeof(uint64_t), 1.25);
-        cand1_.ensure(C * sizeof(uint64_t), 1.25);
+        const size_t key_bytes = ranked ? sizeof(uint32_t) : sizeof(uint64_t);
+        cand0_.ensure(C * key_bytes, 1.25);
+        cand1_.ensure(C * key_bytes, 1.25);
 
         const uint64_t *Ld, *Lp;
         uint64_t *out;
@@ -273,17 +289,35 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             out = nullptr;  // sized once N is known
         }
 
-        const uint64_t *sorted = expand_sort(Ld, F, gsel_.as<GenSel>(), k, cand0_.as<uint64_t>(),
-                                             cand1_.as<uint64_t>(), bit_lo, bit_hi, w_);
-        uint64_t *scratch = sorted == cand0_.as<uint64_t>() ? cand1_.as<uint64_t>() : cand0_.as<uint64_t>();
-        launch_dedup_count(sorted, C, Ld, F, Lp, np, scratch, w_.counter(), w_);
-        const uint64_t N = read_counter();
-        if (N > C || N > room) throw Error(CG_E_DEVICE, "layer size out of range (device error)");
-        if (!keep_all) {
-            lay_[in].ensure(std::max<uint64_t>(N, 1) * sizeof(uint64_t), 1.25);
-            out = lay_[in].as<uint64_t>();
+        uint64_t N = 0;
+        if (ranked) {
+            // candidates as 32-bit lexicographic ranks: half the bytes per
+            // sort pass and only ceil(log2 n!) bits to sort
+            uint32_t *c0 = cand0_.as<uint32_t>(), *c1 = cand1_.as<uint32_t>();
+            launch_expand_ranked(n, Ld, F, gsel_.as<GenSel>(), k, c0, w_);
+            const uint32_t *sorted = radix_sort32(c0, c1, C, 0, rank_bits, w_);
+            uint32_t *scratch = sorted == c0 ? c1 : c0;
+            launch_dedup_count_ranked(n, sorted, C, Ld, F, Lp, np, scratch, w_.counter(), w_);
+            N = read_counter();
+            if (N > C || N > room) throw Error(CG_E_DEVICE, "layer size out of range (device error)");
+            if (!keep_all) {
+                lay_[in].ensure(std::max<uint64_t>(N, 1) * sizeof(uint64_t), 1.25);
+                out = lay_[in].as<uint64_t>();
+            }
+            launch_dedup_gather_ranked(n, scratch, out, keep_all ? out_cap : N, w_);
+        } else {
+            const uint64_t *sorted = expand_sort(Ld, F, gsel_.as<GenSel>(), k, cand0_.as<uint64_t>(),
+                                                 cand1_.as<uint64_t>(), bit_lo, bit_hi, w_);
+            uint64_t *scratch = sorted == cand0_.as<uint64_t>() ? cand1_.as<uint64_t>() : cand0_.as<uint64_t>();
+            launch_dedup_count(sorted, C, Ld, F, Lp, np, scratch, w_.counter(), w_);
+            N = read_counter();
+            if (N > C || N > room) throw Error(CG_E_DEVICE, "layer size out of range (device error)");
+            if (!keep_all) {
+                lay_[in].ensure(std::max<uint64_t>(N, 1) * sizeof(uint64_t), 1.25);
+                out = lay_[in].as<uint64_t>();
+            }
+            launch_dedup_gather(scratch, out, keep_all ? out_cap : N, w_);
         }
-        launch_dedup_gather(scratch, out, keep_all ? out_cap : N, w_);
         if (prof_.on) {
             prof_.collect();
             prof_.bytes[K_DEDUP] += 8.0 * (double)N;

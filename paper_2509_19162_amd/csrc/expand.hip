@@ -14,6 +14,7 @@
 #include "internal.h"
 #include "device_util.h"
 #include "expand_device.h"
+#include "perm_rank.h"
 
 namespace cg {
 
@@ -81,6 +82,19 @@ __global__ __launch_bounds__(kExpandBlock) void expand_kernel(
     }
 }
 
+// Same tiling as expand_kernel; each candidate is stored as its 32-bit
+// lexicographic rank.
+__global__ __launch_bounds__(kExpandBlock) void expand_rank_kernel(
+    const uint64_t *__restrict__ frontier, uint64_t F, const GenSel *__restrict__ gsel,
+    uint32_t *__restrict__ out, uint32_t blocks_per_gen, int n) {
+    const uint32_t g = blockIdx.x / blocks_per_gen;
+    const uint64_t b = blockIdx.x - (uint64_t)g * blocks_per_gen;
+    const GenSel sel = gsel[g];
+    const uint64_t stride = (uint64_t)blocks_per_gen * kExpandBlock;
+    for (uint64_t f = b * kExpandBlock + threadIdx.x; f < F; f += stride)
+        out[(uint64_t)g * F + f] = perm_rank(apply_gensel(frontier[f], sel), n);
+}
+
 __global__ void pack_kernel(int n, const uint8_t *__restrict__ rows, uint64_t count,
                             uint64_t *__restrict__ keys) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -115,6 +129,21 @@ void launch_expand(const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, i
                        frontier, F, d_gsel, out, bpg);
     CG_HIP(hipGetLastError());
     if (w.prof) w.prof->end(K_EXPAND, 8.0 * (double)F * k + 8.0 * (double)F, (double)F * k);
+}
+
+void launch_expand_ranked(int n, const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,
+                          uint32_t *out, PipeWork &w) {
+    if (F == 0 || k == 0) return;
+    uint64_t per = (F + kExpandBlock - 1) / kExpandBlock;
+    uint64_t want = (2048 + (uint64_t)k - 1) / (uint64_t)k;
+    if (want < 8) want = 8;
+    uint32_t bpg = (uint32_t)(per < want ? per : want);
+    if (bpg == 0) bpg = 1;
+    if (w.prof) w.prof->begin(K_EXPAND);
+    hipLaunchKernelGGL(expand_rank_kernel, dim3(bpg * (uint32_t)k), dim3(kExpandBlock), 0, w.stream,
+                       frontier, F, d_gsel, out, bpg, n);
+    CG_HIP(hipGetLastError());
+    if (w.prof) w.prof->end(K_EXPAND, 4.0 * (double)F * k + 8.0 * (double)F, (double)F * k);
 }
 
 void launch_pack(int n, const uint8_t *d_rows, uint64_t count, uint64_t *d_keys,

@@ -160,6 +160,9 @@ int sort_passes(int bit_lo, int bit_hi);
 // holds the result (keys or tmp).
 uint64_t *radix_sort(uint64_t *keys, uint64_t *tmp, uint64_t count, int bit_lo,
                      int bit_hi, PipeWork &w);
+// The same for 32-bit keys (candidates under their lexicographic rank).
+uint32_t *radix_sort32(uint32_t *keys, uint32_t *tmp, uint64_t count, int bit_lo,
+                       int bit_hi, PipeWork &w);
 // Expands frontier[0..F) by the k generators and sorts the k*F candidates on
 // bits [bit_lo, bit_hi); the first pass regenerates candidates from the
 // frontier instead of reading them. Returns buf0 or buf1 (each k*F keys).
@@ -184,6 +187,17 @@ void launch_dedup_count(const uint64_t *sorted, uint64_t C, const uint64_t *a,
                         uint64_t na, const uint64_t *b, uint64_t nb, uint64_t *tmp,
                         uint64_t *d_count, PipeWork &w);
 void launch_dedup_gather(const uint64_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w);
+// The same with candidates as 32-bit lexicographic ranks (n <= 12): the
+// reference layers are ranked as they are read and survivors are written
+// back as packed keys.
+void launch_dedup_count_ranked(int n, const uint32_t *sorted, uint64_t C, const uint64_t *a,
+                               uint64_t na, const uint64_t *b, uint64_t nb, uint32_t *tmp,
+                               uint64_t *d_count, PipeWork &w);
+void launch_dedup_gather_ranked(int n, const uint32_t *tmp, uint64_t *out, uint64_t out_cap,
+                                PipeWork &w);
+// Permute-expand into 32-bit ranks: out[g*F + f] = rank(key(s_f . g)).
+void launch_expand_ranked(int n, const uint64_t *frontier, uint64_t F, const GenSel *d_gsel,
+                          int k, uint32_t *out, PipeWork &w);
 // True once the device's arena exists (buffers then grow to exact sizes).
 bool arena_active();
 uint64_t dedup_status_words(uint64_t C);

@@ -45,13 +45,15 @@ static_assert(kBlock == kRadix, "one thread per digit in the look-back");
 // ---- key sources --------------------------------------------------------------
 // A source maps (tile, index in tile) to a key and knows each tile's length.
 
-struct ArraySrc {
-    const uint64_t *keys;
+template <class K>
+struct ArraySrcT {
+    using Key = K;
+    const K *keys;
     uint64_t count;
     struct Tile {
-        const uint64_t *p;
+        const K *p;
         uint32_t n;
-        __device__ __forceinline__ uint64_t get(uint32_t i) const { return p[i]; }
+        __device__ __forceinline__ K get(uint32_t i) const { return p[i]; }
     };
     __device__ __forceinline__ Tile tile(uint32_t t) const {
         const uint64_t start = (uint64_t)t * kTile;
@@ -59,8 +61,9 @@ struct ArraySrc {
         return Tile{keys + start, (uint32_t)(left < (uint64_t)kTile ? left : (uint64_t)kTile)};
     }
     __host__ __device__ uint32_t tiles() const { return (uint32_t)((count + kTile - 1) / kTile); }
-    void materialize(uint64_t *, PipeWork &) const {}
+    void materialize(K *, PipeWork &) const {}
 };
+using ArraySrc = ArraySrcT<uint64_t>;
 
 // A tile is one frontier block (kTile states) under one generator. Tiles
 // are numbered so that the k tiles of a block are 8 apart: workgroups are
@@ -70,6 +73,7 @@ struct ArraySrc {
 constexpr uint32_t kXcds = 8;
 
 struct ExpandSrc {
+    using Key = uint64_t;
     const uint64_t *frontier;
     uint64_t F;
     const GenSel *gsel;
@@ -126,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void hist_kernel(Src src, uint32_t ntiles, 
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const auto T = src.tile(t);
         for (uint32_t i = threadIdx.x; i < T.n; i += kBlock) {
-            const uint64_t key = T.get(i);
+            const uint64_t key = (uint64_t)T.get(i);
 #pragma unroll
             for (int p = 0; p < kMaxPasses; ++p) {
                 if (p < pd.passes) {
@@ -173,10 +177,11 @@ __global__ void clear_kernel(unsigned long long *__restrict__ a, uint32_t na,
 // ---- 3. one scatter pass -----------------------------------------------------------------
 template <class Src>
 __global__ __launch_bounds__(kBlock) void onesweep_kernel(
-    Src src, uint64_t *__restrict__ out, uint64_t total, int shift, uint32_t dmask,
+    Src src, typename Src::Key *__restrict__ out, uint64_t total, int shift, uint32_t dmask,
     const unsigned long long *__restrict__ digit_base, uint64_t *__restrict__ status,
     uint32_t *__restrict__ ticket, uint32_t epoch, uint32_t *__restrict__ err) {
-    __shared__ uint64_t s_keys[kTile];
+    using K = typename Src::Key;
+    __shared__ __align__(16) K s_keys[kTile];
     __shared__ uint32_t s_cnt[kWaves][kRadix];
     __shared__ uint64_t s_gstart[kRadix];
     __shared__ uint32_t s_lstart[kRadix];
@@ -185,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
 
     // the digit masks of the ranking live in s_keys until the scatter
     uint64_t(*s_match)[kRadix] = reinterpret_cast<uint64_t(*)[kRadix]>(s_keys);
-    static_assert(kWaves * kRadix <= kTile, "match words fit in the key tile");
+    static_assert(kWaves * kRadix * sizeof(uint64_t) <= kTile * sizeof(K), "match words fit in the key tile");
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
@@ -204,11 +209,11 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     // Wave w owns keys [w*1024, (w+1)*1024) of the tile; item j of lane l is
     // key w*1024 + j*64 + l, so (wave, item, lane) order is index order and
     // the per-wave running counts give a stable rank.
-    uint64_t key[kIpt];
+    K key[kIpt];
 #pragma unroll
     for (int j = 0; j < kIpt; ++j) {
         const uint32_t i = wave * kWaveSeg + j * kWave + lane;
-        key[j] = i < nvalid ? T.get(i) : kSentinel;
+        key[j] = i < nvalid ? T.get(i) : (K)kSentinel;
     }
     // Peers (lanes of this wave holding the same digit) come from an LDS
     // mask per digit: every lane ORs its lane bit into its digit's word,
@@ -291,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     __syncthreads();
 
     for (uint32_t i = tid; i < nvalid; i += kBlock) {
-        const uint64_t k = s_keys[i];
+        const K k = s_keys[i];
         const uint32_t d = (uint32_t)(k >> shift) & dmask;
         const uint64_t gpos = s_gstart[d] + (i - s_lstart[d]);
         if (gpos < total)
@@ -321,9 +326,11 @@ uint32_t hist_grid(uint32_t ntiles) {
 constexpr uint64_t kSkipCheckMin = 1ull << 22;
 
 template <class Src>
-uint64_t *run_sort(const Src &first_src, uint64_t count, uint64_t *buf0, uint64_t *buf1,
-                   int bit_lo, int bit_hi, PipeWork &w, bool fused_first,
-                   double first_read_bytes, const uint64_t *array_in) {
+typename Src::Key *run_sort(const Src &first_src, uint64_t count, typename Src::Key *buf0,
+                            typename Src::Key *buf1, int bit_lo, int bit_hi, PipeWork &w, bool fused_first,
+                            double first_read_bytes, const typename Src::Key *array_in) {
+    using K = typename Src::Key;
+    constexpr double kb = (double)sizeof(K);
     const PassDesc pd = make_passes(bit_lo, bit_hi);
     if (pd.passes > kMaxPasses) throw Error(-1, "sort bit range needs more than 8 passes");
     unsigned long long *hist = w.hist.as<unsigned long long>();
@@ -367,13 +374,13 @@ uint64_t *run_sort(const Src &first_src, uint64_t count, uint64_t *buf0, uint64_
         for (int p = 0; p < pd.passes; ++p) keep[nkeep++] = p;
     }
     if (nkeep == 0) {
-        if (!fused_first) return const_cast<uint64_t *>(array_in);
+        if (!fused_first) return const_cast<K *>(array_in);
         first_src.materialize(buf0, w);  // contiguous, generator-major
         return buf0;
     }
 
-    uint64_t *cur_out = buf0;
-    const uint64_t *cur_in = nullptr;
+    K *cur_out = buf0;
+    const K *cur_in = nullptr;
     for (int q = 0; q < nkeep; ++q) {
         const int p = keep[q];
         const uint32_t epoch = w.next_epoch();
@@ -384,20 +391,20 @@ uint64_t *run_sort(const Src &first_src, uint64_t count, uint64_t *buf0, uint64_
                                cur_out, count, pd.shift[p], pd.mask[p], base + p * kRadix,
                                w.status.as<uint64_t>(), w.tickets() + p, epoch, w.err());
             CG_HIP(hipGetLastError());
-            if (w.prof) w.prof->end(kind, first_read_bytes + 8.0 * (double)count, (double)count);
+            if (w.prof) w.prof->end(kind, first_read_bytes + kb * (double)count, (double)count);
         } else {
-            const ArraySrc s{cur_in, count};
+            const ArraySrcT<K> s{cur_in, count};
             if (w.prof) w.prof->begin(K_SORT);
-            hipLaunchKernelGGL(onesweep_kernel<ArraySrc>, dim3(s.tiles()), dim3(kBlock), 0, w.stream,
+            hipLaunchKernelGGL(onesweep_kernel<ArraySrcT<K>>, dim3(s.tiles()), dim3(kBlock), 0, w.stream,
                                s, cur_out, count, pd.shift[p], pd.mask[p], base + p * kRadix,
                                w.status.as<uint64_t>(), w.tickets() + p, epoch, w.err());
             CG_HIP(hipGetLastError());
-            if (w.prof) w.prof->end(K_SORT, 16.0 * (double)count, (double)count);
+            if (w.prof) w.prof->end(K_SORT, 2.0 * kb * (double)count, (double)count);
         }
         cur_in = cur_out;
         cur_out = (cur_out == buf0) ? buf1 : buf0;
     }
-    return const_cast<uint64_t *>(cur_in);
+    return const_cast<K *>(cur_in);
 }
 
 }  // namespace
@@ -419,6 +426,14 @@ uint64_t *radix_sort(uint64_t *keys, uint64_t *tmp, uint64_t count, int bit_lo, 
     const ArraySrc src{keys, count};
     // pass 0 reads `keys` and writes `tmp`; then they alternate
     return run_sort(src, count, tmp, keys, bit_lo, bit_hi, w, false, 8.0 * (double)count, keys);
+}
+
+uint32_t *radix_sort32(uint32_t *keys, uint32_t *tmp, uint64_t count, int bit_lo, int bit_hi,
+                       PipeWork &w) {
+    if (count <= 1 || bit_lo >= bit_hi) return keys;
+    w.ensure_status(sort_status_words(count));
+    const ArraySrcT<uint32_t> src{keys, count};
+    return run_sort(src, count, tmp, keys, bit_lo, bit_hi, w, false, 4.0 * (double)count, keys);
 }
 
 uint64_t *expand_sort(const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,

@@ -1,0 +1,75 @@
+"""Host-side logic of the library checked on the CPU (no device calls):
+lexicographic rank/unrank of packed keys and the byte-permute selector
+tables of the expand step (v_perm_b32 semantics emulated on the host)."""
+
+import ctypes
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from paper_2509_19162_amd import _native as N
+from paper_2509_19162_amd import inputs as I
+
+
+def pack(n, rows):
+    rows = np.asarray(rows, dtype=np.uint64).reshape(-1, n)
+    shifts = np.array([4 * (n - 1 - i) for i in range(n)], dtype=np.uint64)
+    return np.bitwise_or.reduce(rows << shifts, axis=1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7])
+def test_rank_is_lexicographic_index(n):
+    perms = list(itertools.permutations(range(n)))  # lexicographic order
+    keys = np.ascontiguousarray(pack(n, perms))
+    ranks = np.zeros(len(perms), dtype=np.uint32)
+    rc = N.lib().cg_test_rank(n, keys.ctypes.data_as(N.u64p), len(perms),
+                              ranks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), 0, None)
+    assert rc == 0
+    assert np.array_equal(ranks, np.arange(len(perms), dtype=np.uint32))
+    back = np.zeros(len(perms), dtype=np.uint64)
+    rc = N.lib().cg_test_unrank(n, ranks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), len(perms),
+                                back.ctypes.data_as(N.u64p), 0, None)
+    assert rc == 0 and np.array_equal(back, keys)
+
+
+@pytest.mark.parametrize("n", [10, 12])
+def test_rank_sampled_large_n(n):
+    rng = np.random.default_rng(n)
+    perms = [list(map(int, rng.permutation(n))) for _ in range(500)]
+    keys = np.ascontiguousarray(pack(n, perms))
+    ranks = np.zeros(len(perms), dtype=np.uint32)
+    N.lib().cg_test_rank(n, keys.ctypes.data_as(N.u64p), len(perms),
+                         ranks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), 0, None)
+    # Lehmer code by its definition, in Python integers
+    for p, r in zip(perms, ranks):
+        code = sum(sum(1 for j in range(i + 1, n) if p[j] < p[i]) * math.factorial(n - 1 - i) for i in range(n))
+        assert code == int(r)
+    order = np.argsort(keys, kind="stable")
+    assert np.all(np.diff(ranks[order].astype(np.int64)) > 0)  # order preserved
+
+
+def test_rank_rejects_bad_input():
+    r = np.zeros(1, dtype=np.uint32)
+    k = np.zeros(1, dtype=np.uint64)
+    assert N.lib().cg_test_rank(13, k.ctypes.data_as(N.u64p), 1,
+                                r.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), 0, None) == N.CG_E_INVAL
+    r[0] = 6
+    assert N.lib().cg_test_unrank(3, r.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), 1,
+                                  k.ctypes.data_as(N.u64p), 0, None) == N.CG_E_INVAL
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 9, 12, 15, 16])
+def test_host_expand_selectors_match_gather(n):
+    rng = np.random.default_rng(100 + n)
+    gens = [list(map(int, rng.permutation(n))) for _ in range(5)] + I.coxeter(n)[:2]
+    rows = np.stack([rng.permutation(n) for _ in range(200)]).astype(np.uint8)
+    keys = np.ascontiguousarray(pack(n, rows))
+    g = np.ascontiguousarray(np.asarray(gens, dtype=np.uint8))
+    out = np.zeros(len(gens) * len(keys), dtype=np.uint64)
+    rc = N.lib().cg_test_host_expand(n, g.ctypes.data_as(N.u8p), len(gens), keys.ctypes.data_as(N.u64p),
+                                     len(keys), out.ctypes.data_as(N.u64p))
+    assert rc == 0
+    expected = np.concatenate([pack(n, rows[:, gg]) for gg in gens])
+    assert np.array_equal(out, expected)
