@@ -15,13 +15,18 @@
 //   * a separate small kernel first finds, for every tile, the slice of each
 //     reference layer between the tile's first and last key (binary
 //     searches, one thread each), so no tile waits on a search;
-//   * the slice is streamed through LDS in chunks and every thread looks up
-//     its 16 keys in it with 16 interleaved branchless binary searches;
+//   * every reference key of the slice (usually far fewer than the
+//     candidates) looks itself up in the tile, sorted in LDS, with a
+//     branchless binary search and marks the equal candidate; when a small
+//     candidate array meets large reference layers the marking runs over
+//     the whole reference layers instead, one thread per reference key;
 //   * survivors are compacted within the tile and parked in a scratch
 //     buffer with their count; no tile waits on another;
 //   * a small scan turns the counts into offsets, and a gather moves each
 //     tile's survivors to their final place, so the new layer comes out
 //     sorted and contiguous.
+#include <algorithm>
+
 #include "internal.h"
 #include "device_util.h"
 #include "perm_rank.h"
@@ -34,7 +39,8 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kIpt = 16;
 constexpr int kTile = kBlock * kIpt;  // 4096
-constexpr int kRef = 2048;            // reference keys per LDS chunk
+// largest candidate array looked up from the reference side (4 MB of u32)
+constexpr uint64_t kMarkMaxCandidates = 1u << 20;
 
 __device__ __forceinline__ uint32_t pad(uint32_t i) { return i + (i >> 4); }
 
@@ -47,11 +53,12 @@ struct PackedKeys {
     __device__ __forceinline__ K from_layer(uint64_t x) const { return x; }
     __device__ __forceinline__ uint64_t to_layer(K x) const { return x; }
 };
+template <int N>
 struct RankedKeys {
     using K = uint32_t;
     int n;
-    __device__ __forceinline__ K from_layer(uint64_t x) const { return perm_rank(x, n); }
-    __device__ __forceinline__ uint64_t to_layer(K x) const { return perm_unrank(x, n); }
+    __device__ __forceinline__ K from_layer(uint64_t x) const { return perm_rank_t<N>(x); }
+    __device__ __forceinline__ uint64_t to_layer(K x) const { return perm_unrank_t<N>(x); }
 };
 
 // bounds[4t + 0/1]: lower bound of tile t's first key / upper bound of its
@@ -85,14 +92,39 @@ __global__ __launch_bounds__(256) void tile_bounds_kernel(
 // Phase 1: one tile per block (no inter-tile dependency): unique + set
 // difference, survivors compacted within the tile into tmp[tile*kTile ..]
 // and counted in cnt[tile].
+// Reference-heavy layers (a small candidate array against large reference
+// layers, as at the end of a search): each reference key is looked up in the
+// whole sorted candidate array, which is small enough to stay in the caches,
+// and the first equal candidate is flagged. With per-tile slices all those
+// references would fall to the one or two blocks whose key range covers them.
+template <class P>
+__global__ __launch_bounds__(256) void mark_refs_kernel(P pol, const typename P::K *__restrict__ S, uint64_t C,
+                                                        const uint64_t *__restrict__ R, uint64_t nr,
+                                                        uint8_t *__restrict__ kill) {
+    using K = typename P::K;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nr; i += stride) {
+        const K key = pol.from_layer(R[i]);
+        uint64_t lo = 0, hi = C;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (S[mid] < key)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        if (lo < C && S[lo] == key) kill[lo] = 1;
+    }
+}
+
 template <class P>
 __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
     P pol, const typename P::K *__restrict__ S, uint64_t C, const uint64_t *__restrict__ A, uint64_t na,
     const uint64_t *__restrict__ B, uint64_t nb, const uint64_t *__restrict__ bounds,
-    typename P::K *__restrict__ tmp, uint32_t *__restrict__ cnt) {
+    const uint8_t *__restrict__ gkill, typename P::K *__restrict__ tmp, uint32_t *__restrict__ cnt) {
     using K = typename P::K;
     __shared__ K s_keys[kTile + kTile / 16];
-    __shared__ K s_ref[kRef];
+    __shared__ uint8_t s_kill[kTile];
     __shared__ uint32_t s_scan[kWaves];
 
     const uint32_t tid = threadIdx.x;
@@ -105,10 +137,14 @@ __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
     for (int j = 0; j < kIpt; ++j) {
         const uint32_t i = j * kBlock + tid;
         s_keys[pad(i)] = i < nvalid ? S[base + i] : (K)kSentinel;
+        s_kill[i] = (gkill && i < nvalid) ? gkill[base + i] : 0;
     }
     const bool has_prev = base > 0;
     const K prev_global = has_prev ? S[base - 1] : (K)0;
     uint64_t bnd[4] = {0, 0, 0, 0};
+    if (gkill) {
+        na = nb = 0;  // matches already flagged by mark_refs_kernel
+    }
     if (na) {
         bnd[0] = bounds[4 * (uint64_t)tile];
         bnd[1] = bounds[4 * (uint64_t)tile + 1];
@@ -116,6 +152,26 @@ __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
     if (nb) {
         bnd[2] = bounds[4 * (uint64_t)tile + 2];
         bnd[3] = bounds[4 * (uint64_t)tile + 3];
+    }
+    __syncthreads();
+
+    // Reference keys in the tile's range are far fewer than candidates: each
+    // one looks itself up in the sorted tile (12 LDS probes) and marks the
+    // first equal candidate; later copies of a key are dropped as repeats.
+    for (int r = 0; r < 2; ++r) {
+        const uint64_t *R = r == 0 ? A : B;
+        const uint64_t lo = bnd[2 * r], hi = bnd[2 * r + 1];
+        for (uint64_t i = lo + tid; i < hi; i += kBlock) {
+            const K key = pol.from_layer(R[i]);
+            uint32_t pos = 0, len = nvalid;
+            while (len > 1) {
+                const uint32_t half = len >> 1;
+                pos = s_keys[pad(pos + half)] < key ? pos + half : pos;
+                len -= half;
+            }
+            const uint32_t lb = pos + (s_keys[pad(pos)] < key ? 1u : 0u);
+            if (lb < nvalid && s_keys[pad(lb)] == key) s_kill[lb] = 1;
+        }
     }
     __syncthreads();
 
@@ -137,40 +193,7 @@ __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
             prev = prev_global;
             first = !has_prev;
         }
-        if (idx < nvalid && (first || k[j] != prev)) keep |= 1u << j;
-    }
-
-    for (int r = 0; r < 2; ++r) {
-        const uint64_t *R = r == 0 ? A : B;
-        const uint64_t lo = bnd[2 * r], hi = bnd[2 * r + 1];
-        for (uint64_t c0 = lo; c0 < hi; c0 += kRef) {
-            const uint64_t rem = hi - c0;
-            const uint32_t m = (uint32_t)(rem < (uint64_t)kRef ? rem : (uint64_t)kRef);
-            for (uint32_t i = tid; i < m; i += kBlock) s_ref[i] = pol.from_layer(R[c0 + i]);
-            __syncthreads();
-            if (keep) {
-                // 16 independent branchless lower-bound searches, advanced
-                // in lockstep so their LDS latencies overlap
-                uint32_t pos[kIpt];
-#pragma unroll
-                for (int j = 0; j < kIpt; ++j) pos[j] = 0;
-                uint32_t len = m;
-                while (len > 1) {
-                    const uint32_t half = len >> 1;
-#pragma unroll
-                    for (int j = 0; j < kIpt; ++j)
-                        pos[j] = s_ref[pos[j] + half] < k[j] ? pos[j] + half : pos[j];
-                    len -= half;
-                }
-#pragma unroll
-                for (int j = 0; j < kIpt; ++j) {
-                    const K v = s_ref[pos[j]];
-                    const uint32_t lb = pos[j] + (v < k[j] ? 1u : 0u);
-                    if (lb < m && s_ref[lb] == k[j]) keep &= ~(1u << j);
-                }
-            }
-            __syncthreads();
-        }
+        if (idx < nvalid && (first || k[j] != prev) && !s_kill[idx]) keep |= 1u << j;
     }
 
     uint32_t total;
@@ -184,6 +207,11 @@ __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
     __syncthreads();
     for (uint32_t i = tid; i < total; i += kBlock) tmp[base + i] = s_keys[pad(i)];
     if (tid == 0) cnt[tile] = total;
+}
+
+__global__ void fill_bytes_kernel(uint8_t *__restrict__ p, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 // Phase 2: exclusive prefix of the per-tile counts, 1024 tiles per block,
@@ -282,13 +310,29 @@ void dedup_count_impl(P pol, const typename P::K *sorted, uint64_t C, const uint
     w.tile_off.ensure((size_t)ntiles * sizeof(uint64_t), 1.25);
     const uint32_t epoch = w.next_epoch();
     if (w.prof) w.prof->begin(K_DEDUP);
-    if (na || nb) {
+    const bool ref_heavy = C <= kMarkMaxCandidates && na + nb > 4 * C;
+    const uint8_t *gkill = nullptr;
+    if (ref_heavy) {
+        w.kill.ensure(C + 64, 1.25);
+        hipLaunchKernelGGL(fill_bytes_kernel, dim3((uint32_t)((C + 255) / 256)), dim3(256), 0, w.stream,
+                           w.kill.as<uint8_t>(), C);
+        CG_HIP(hipGetLastError());
+        auto blocks = [](uint64_t m) { return (uint32_t)std::min<uint64_t>((m + 255) / 256, 1u << 16); };
+        if (na)
+            hipLaunchKernelGGL(mark_refs_kernel<P>, dim3(blocks(na)), dim3(256), 0, w.stream, pol, sorted, C, a, na,
+                               w.kill.as<uint8_t>());
+        if (nb)
+            hipLaunchKernelGGL(mark_refs_kernel<P>, dim3(blocks(nb)), dim3(256), 0, w.stream, pol, sorted, C, b, nb,
+                               w.kill.as<uint8_t>());
+        CG_HIP(hipGetLastError());
+        gkill = w.kill.as<const uint8_t>();
+    } else if (na || nb) {
         hipLaunchKernelGGL(tile_bounds_kernel<P>, dim3((4 * ntiles + 255) / 256), dim3(256), 0, w.stream,
                            pol, sorted, C, a, na, b, nb, w.bounds.as<uint64_t>(), ntiles);
         CG_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(dedup_local_kernel<P>, dim3(ntiles), dim3(kBlock), 0, w.stream, pol, sorted, C, a,
-                       na, b, nb, w.bounds.as<const uint64_t>(), tmp, w.tile_cnt.as<uint32_t>());
+                       na, b, nb, w.bounds.as<const uint64_t>(), gkill, tmp, w.tile_cnt.as<uint32_t>());
     CG_HIP(hipGetLastError());
     hipLaunchKernelGGL(count_scan_kernel, dim3(nscan), dim3(kScanBlock), 0, w.stream,
                        w.tile_cnt.as<const uint32_t>(), ntiles, w.tile_off.as<uint64_t>(), d_count,
@@ -328,11 +372,13 @@ void launch_dedup_gather(const uint64_t *tmp, uint64_t *out, uint64_t out_cap, P
 void launch_dedup_count_ranked(int n, const uint32_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,
                                const uint64_t *b, uint64_t nb, uint32_t *tmp, uint64_t *d_count,
                                PipeWork &w) {
-    dedup_count_impl(RankedKeys{n}, sorted, C, a, na, b, nb, tmp, d_count, w);
+    with_rank_n(n, [&](auto NN) {
+        dedup_count_impl(RankedKeys<decltype(NN)::value>{n}, sorted, C, a, na, b, nb, tmp, d_count, w);
+    });
 }
 
 void launch_dedup_gather_ranked(int n, const uint32_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w) {
-    dedup_gather_impl(RankedKeys{n}, tmp, out, out_cap, w);
+    with_rank_n(n, [&](auto NN) { dedup_gather_impl(RankedKeys<decltype(NN)::value>{n}, tmp, out, out_cap, w); });
 }
 
 void launch_dedup(const uint64_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,

@@ -119,7 +119,8 @@ Engine::~Engine() {
     if (host_small_) (void)hipHostFree(host_small_);
     // buffers go back to the device cache while their stream still exists
     for (DevBuf *b : {&gsel_, &cand0_, &cand1_, &lay_[0], &lay_[1], &lay_[2], &arena_, &stage_}) b->release();
-    for (DevBuf *b : {&w_.hist, &w_.base, &w_.small, &w_.status, &w_.bounds, &w_.tile_cnt, &w_.tile_off})
+    for (DevBuf *b : {&w_.hist, &w_.base, &w_.small, &w_.status, &w_.bounds, &w_.tile_cnt, &w_.tile_off,
+                      &w_.kill})
         b->release();
     if (own_stream_) {
         (void)hipStreamSynchronize(stream_);
@@ -294,8 +295,7 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             // candidates as 32-bit lexicographic ranks: half the bytes per
             // sort pass and only ceil(log2 n!) bits to sort
             uint32_t *c0 = cand0_.as<uint32_t>(), *c1 = cand1_.as<uint32_t>();
-            launch_expand_ranked(n, Ld, F, gsel_.as<GenSel>(), k, c0, w_);
-            const uint32_t *sorted = radix_sort32(c0, c1, C, 0, rank_bits, w_);
+            const uint32_t *sorted = expand_rank_sort(n, Ld, F, gsel_.as<GenSel>(), k, c0, c1, rank_bits, w_);
             uint32_t *scratch = sorted == c0 ? c1 : c0;
             launch_dedup_count_ranked(n, sorted, C, Ld, F, Lp, np, scratch, w_.counter(), w_);
             N = read_counter();

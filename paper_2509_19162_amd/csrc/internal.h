@@ -124,6 +124,7 @@ struct PipeWork {
     DevBuf bounds;   // uint64 [tiles][4]: reference-layer slices of dedup tiles
     DevBuf tile_cnt; // uint32 [tiles]: survivors per dedup tile
     DevBuf tile_off; // uint64 [tiles]: output offset per dedup tile
+    DevBuf kill;     // uint8 [C]: candidates found in a reference layer
     uint32_t epoch = 0;  // 16-bit epoch of the look-back words
     uint32_t dedup_tiles = 0;  // tiles of the last launch_dedup_count
     hipStream_t stream = nullptr;
@@ -160,6 +161,11 @@ int sort_passes(int bit_lo, int bit_hi);
 // holds the result (keys or tmp).
 uint64_t *radix_sort(uint64_t *keys, uint64_t *tmp, uint64_t count, int bit_lo,
                      int bit_hi, PipeWork &w);
+// Expands frontier[0..F) into the 32-bit ranks of the k*F candidates
+// (n <= 12) while counting the digits of every pass, then sorts them on
+// bits [0, rank_bits). Returns buf0 or buf1 (each k*F words).
+uint32_t *expand_rank_sort(int n, const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,
+                           uint32_t *buf0, uint32_t *buf1, int rank_bits, PipeWork &w);
 // The same for 32-bit keys (candidates under their lexicographic rank).
 uint32_t *radix_sort32(uint32_t *keys, uint32_t *tmp, uint64_t count, int bit_lo,
                        int bit_hi, PipeWork &w);

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace cg {
 
@@ -44,6 +45,63 @@ __host__ __device__ __forceinline__ uint64_t perm_unrank(uint32_t rank, int n) {
         key |= v << (4 * (n - 1 - i));
     }
     return key;
+}
+
+// The same with n fixed at compile time: the loops unroll, shifts become
+// constants and the divisions of the unrank become multiplications.
+template <int N>
+__host__ __device__ __forceinline__ uint32_t perm_rank_t(uint64_t key) {
+    uint32_t rank = 0, used = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const uint32_t v = (uint32_t)(key >> (4 * (N - 1 - i))) & 15u;
+        const uint32_t c = v - (uint32_t)__builtin_popcount(used & ((1u << v) - 1u));
+        rank = rank * (uint32_t)(N - i) + c;
+        used |= 1u << v;
+    }
+    return rank;
+}
+
+template <int N>
+__host__ __device__ __forceinline__ uint64_t perm_unrank_t(uint32_t rank) {
+    uint32_t c[N > 0 ? N : 1];
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        c[i] = rank % (uint32_t)(N - i);
+        rank /= (uint32_t)(N - i);
+    }
+    uint64_t avail = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) avail |= (uint64_t)j << (4 * j);
+    uint64_t key = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const uint32_t sh = 4 * c[i];
+        const uint64_t v = (avail >> sh) & 15u;
+        const uint64_t low = avail & ((1ull << sh) - 1ull);
+        avail = low | ((avail >> (sh + 4)) << sh);
+        key |= v << (4 * (N - 1 - i));
+    }
+    return key;
+}
+
+// Calls f(std::integral_constant<int, N>{}) for the runtime n in 1..12.
+template <class F>
+void with_rank_n(int n, F &&f) {
+    switch (n) {
+        case 1: f(std::integral_constant<int, 1>{}); break;
+        case 2: f(std::integral_constant<int, 2>{}); break;
+        case 3: f(std::integral_constant<int, 3>{}); break;
+        case 4: f(std::integral_constant<int, 4>{}); break;
+        case 5: f(std::integral_constant<int, 5>{}); break;
+        case 6: f(std::integral_constant<int, 6>{}); break;
+        case 7: f(std::integral_constant<int, 7>{}); break;
+        case 8: f(std::integral_constant<int, 8>{}); break;
+        case 9: f(std::integral_constant<int, 9>{}); break;
+        case 10: f(std::integral_constant<int, 10>{}); break;
+        case 11: f(std::integral_constant<int, 11>{}); break;
+        default: f(std::integral_constant<int, 12>{}); break;
+    }
 }
 
 }  // namespace cg

@@ -24,6 +24,7 @@
 #include "internal.h"
 #include "device_util.h"
 #include "expand_device.h"
+#include "perm_rank.h"
 
 namespace cg {
 
@@ -33,12 +34,16 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-#ifndef CG_SORT_IPT
-#define CG_SORT_IPT 16
-#endif
-constexpr int kIpt = CG_SORT_IPT;     // keys per thread
-constexpr int kTile = kBlock * kIpt;  // 4096 keys
-constexpr int kWaveSeg = kWave * kIpt;  // keys owned by one wave
+// Keys per thread: 16 for 64-bit keys (4096-key tiles), 32 for 32-bit keys
+// (8192-key tiles). Both fill 32 KB of LDS per tile; the longer tiles of
+// 32-bit keys halve the per-tile fixed cost (look-back, digit scan).
+template <class K>
+struct TileOf {
+    static constexpr int ipt = sizeof(K) == 4 ? 32 : 16;
+    static constexpr int tile = kBlock * ipt;
+    static constexpr int wave_seg = kWave * ipt;  // keys owned by one wave
+};
+constexpr int kTile = TileOf<uint64_t>::tile;  // the shortest tile: sizes look-back state
 
 static_assert(kBlock == kRadix, "one thread per digit in the look-back");
 
@@ -55,12 +60,13 @@ struct ArraySrcT {
         uint32_t n;
         __device__ __forceinline__ K get(uint32_t i) const { return p[i]; }
     };
+    static constexpr uint64_t kLen = TileOf<K>::tile;
     __device__ __forceinline__ Tile tile(uint32_t t) const {
-        const uint64_t start = (uint64_t)t * kTile;
+        const uint64_t start = (uint64_t)t * kLen;
         const uint64_t left = count - start;
-        return Tile{keys + start, (uint32_t)(left < (uint64_t)kTile ? left : (uint64_t)kTile)};
+        return Tile{keys + start, (uint32_t)(left < kLen ? left : kLen)};
     }
-    __host__ __device__ uint32_t tiles() const { return (uint32_t)((count + kTile - 1) / kTile); }
+    __host__ __device__ uint32_t tiles() const { return (uint32_t)((count + kLen - 1) / kLen); }
     void materialize(K *, PipeWork &) const {}
 };
 using ArraySrc = ArraySrcT<uint64_t>;
@@ -156,6 +162,57 @@ __global__ __launch_bounds__(kBlock) void hist_kernel(Src src, uint32_t ntiles, 
     }
 }
 
+// ---- 1b. ranked expand with the histograms of every pass --------------------------
+// Each block takes a contiguous run of frontier states for one generator,
+// writes the candidates' 32-bit ranks (generator-major, out[g*F + f]) and
+// counts their digits for every pass (runs of equal digits per thread are
+// added with one LDS atomic), so the sort needs no separate histogram read.
+template <int N>
+__global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
+    const uint64_t *__restrict__ frontier, uint64_t F, const GenSel *__restrict__ gsel,
+    uint32_t *__restrict__ out, uint32_t blocks_per_gen, PassDesc pd, unsigned long long *__restrict__ ghist) {
+    __shared__ uint32_t s_h[kMaxPasses][kRadix];
+    for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kBlock) (&s_h[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t g = blockIdx.x / blocks_per_gen;
+    const uint64_t b = blockIdx.x - (uint64_t)g * blocks_per_gen;
+    const GenSel sel = gsel[g];
+    const uint64_t per = (F + blocks_per_gen - 1) / blocks_per_gen;  // contiguous share
+    const uint64_t lo = b * per;
+    const uint64_t hi = lo + per < F ? lo + per : F;
+    uint32_t cur[kMaxPasses], run[kMaxPasses];
+#pragma unroll
+    for (int p = 0; p < kMaxPasses; ++p) {
+        cur[p] = 0;
+        run[p] = 0;
+    }
+    for (uint64_t f = lo + threadIdx.x; f < hi; f += kBlock) {
+        const uint32_t r = perm_rank_t<N>(apply_gensel(frontier[f], sel));
+        out[(uint64_t)g * F + f] = r;
+#pragma unroll
+        for (int p = 0; p < kMaxPasses; ++p) {
+            if (p < pd.passes) {
+                const uint32_t d = (r >> pd.shift[p]) & pd.mask[p];
+                if (d != cur[p]) {
+                    if (run[p]) atomicAdd(&s_h[p][cur[p]], run[p]);
+                    cur[p] = d;
+                    run[p] = 1;
+                } else {
+                    ++run[p];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < kMaxPasses; ++p)
+        if (p < pd.passes && run[p]) atomicAdd(&s_h[p][cur[p]], run[p]);
+    __syncthreads();
+    for (int p = 0; p < pd.passes; ++p) {
+        const uint32_t c = s_h[p][threadIdx.x];
+        if (c) atomicAdd(&ghist[p * kRadix + threadIdx.x], (unsigned long long)c);
+    }
+}
+
 // ---- 2. digit offsets ---------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void digit_scan_kernel(const unsigned long long *__restrict__ ghist,
                                                             unsigned long long *__restrict__ gbase) {
@@ -181,7 +238,10 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     const unsigned long long *__restrict__ digit_base, uint64_t *__restrict__ status,
     uint32_t *__restrict__ ticket, uint32_t epoch, uint32_t *__restrict__ err) {
     using K = typename Src::Key;
-    __shared__ __align__(16) K s_keys[kTile];
+    constexpr int kIpt = TileOf<K>::ipt;
+    constexpr int kTileK = TileOf<K>::tile;
+    constexpr int kWaveSeg = TileOf<K>::wave_seg;
+    __shared__ __align__(16) K s_keys[kTileK];
     __shared__ uint32_t s_cnt[kWaves][kRadix];
     __shared__ uint64_t s_gstart[kRadix];
     __shared__ uint32_t s_lstart[kRadix];
@@ -190,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
 
     // the digit masks of the ranking live in s_keys until the scatter
     uint64_t(*s_match)[kRadix] = reinterpret_cast<uint64_t(*)[kRadix]>(s_keys);
-    static_assert(kWaves * kRadix * sizeof(uint64_t) <= kTile * sizeof(K), "match words fit in the key tile");
+    static_assert(kWaves * kRadix * sizeof(uint64_t) <= kTileK * sizeof(K), "match words fit in the key tile");
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
@@ -206,8 +266,8 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     const auto T = src.tile(tile);
     const uint32_t nvalid = T.n;
 
-    // Wave w owns keys [w*1024, (w+1)*1024) of the tile; item j of lane l is
-    // key w*1024 + j*64 + l, so (wave, item, lane) order is index order and
+    // Wave w owns keys [w*S, (w+1)*S) of the tile (S = kWaveSeg); item j of
+    // lane l is key w*S + j*64 + l, so (wave, item, lane) order is index order and
     // the per-wave running counts give a stable rank.
     K key[kIpt];
 #pragma unroll
@@ -328,7 +388,8 @@ constexpr uint64_t kSkipCheckMin = 1ull << 22;
 template <class Src>
 typename Src::Key *run_sort(const Src &first_src, uint64_t count, typename Src::Key *buf0,
                             typename Src::Key *buf1, int bit_lo, int bit_hi, PipeWork &w, bool fused_first,
-                            double first_read_bytes, const typename Src::Key *array_in) {
+                            double first_read_bytes, const typename Src::Key *array_in,
+                            bool hist_ready = false) {
     using K = typename Src::Key;
     constexpr double kb = (double)sizeof(K);
     const PassDesc pd = make_passes(bit_lo, bit_hi);
@@ -336,18 +397,19 @@ typename Src::Key *run_sort(const Src &first_src, uint64_t count, typename Src::
     unsigned long long *hist = w.hist.as<unsigned long long>();
     unsigned long long *base = w.base.as<unsigned long long>();
 
-    if (w.prof) w.prof->begin(K_AUX);
-    hipLaunchKernelGGL(clear_kernel, dim3(8), dim3(256), 0, w.stream, hist,
-                       (uint32_t)(kMaxPasses * kRadix), w.tickets(), 32u);
-    CG_HIP(hipGetLastError());
-    if (w.prof) w.prof->end(K_AUX, 0, 0);
-
     const uint32_t t0 = first_src.tiles();
-    if (w.prof) w.prof->begin(K_HIST);
-    hipLaunchKernelGGL(hist_kernel<Src>, dim3(hist_grid(t0)), dim3(kBlock), 0, w.stream, first_src,
-                       t0, pd, hist);
-    CG_HIP(hipGetLastError());
-    if (w.prof) w.prof->end(K_HIST, first_read_bytes, (double)count);
+    if (!hist_ready) {
+        if (w.prof) w.prof->begin(K_AUX);
+        hipLaunchKernelGGL(clear_kernel, dim3(8), dim3(256), 0, w.stream, hist,
+                           (uint32_t)(kMaxPasses * kRadix), w.tickets(), 32u);
+        CG_HIP(hipGetLastError());
+        if (w.prof) w.prof->end(K_AUX, 0, 0);
+        if (w.prof) w.prof->begin(K_HIST);
+        hipLaunchKernelGGL(hist_kernel<Src>, dim3(hist_grid(t0)), dim3(kBlock), 0, w.stream, first_src,
+                           t0, pd, hist);
+        CG_HIP(hipGetLastError());
+        if (w.prof) w.prof->end(K_HIST, first_read_bytes, (double)count);
+    }
 
     if (w.prof) w.prof->begin(K_SCAN);
     hipLaunchKernelGGL(digit_scan_kernel, dim3(pd.passes), dim3(kBlock), 0, w.stream, hist, base);
@@ -434,6 +496,35 @@ uint32_t *radix_sort32(uint32_t *keys, uint32_t *tmp, uint64_t count, int bit_lo
     w.ensure_status(sort_status_words(count));
     const ArraySrcT<uint32_t> src{keys, count};
     return run_sort(src, count, tmp, keys, bit_lo, bit_hi, w, false, 4.0 * (double)count, keys);
+}
+
+uint32_t *expand_rank_sort(int n, const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,
+                           uint32_t *buf0, uint32_t *buf1, int rank_bits, PipeWork &w) {
+    const uint64_t C = F * (uint64_t)k;
+    if (C == 0) return buf0;
+    w.ensure_status(sort_status_words(C));
+    const PassDesc pd = make_passes(0, rank_bits);
+    unsigned long long *hist = w.hist.as<unsigned long long>();
+    if (w.prof) w.prof->begin(K_AUX);
+    hipLaunchKernelGGL(clear_kernel, dim3(8), dim3(256), 0, w.stream, hist, (uint32_t)(kMaxPasses * kRadix),
+                       w.tickets(), 32u);
+    CG_HIP(hipGetLastError());
+    if (w.prof) w.prof->end(K_AUX, 0, 0);
+    uint64_t per = (F + kBlock - 1) / kBlock;
+    uint64_t want = (2048 + (uint64_t)k - 1) / (uint64_t)k;
+    if (want < 8) want = 8;
+    uint32_t bpg = (uint32_t)(per < want ? per : want);
+    if (bpg == 0) bpg = 1;
+    if (w.prof) w.prof->begin(K_EXPAND);
+    with_rank_n(n, [&](auto NN) {
+        hipLaunchKernelGGL(expand_rank_hist_kernel<decltype(NN)::value>, dim3(bpg * (uint32_t)k), dim3(kBlock), 0,
+                           w.stream, frontier, F, d_gsel, buf0, bpg, pd, hist);
+    });
+    CG_HIP(hipGetLastError());
+    if (w.prof) w.prof->end(K_EXPAND, 8.0 * (double)F + 4.0 * (double)C, (double)C);
+    if (rank_bits <= 0) return buf0;
+    const ArraySrcT<uint32_t> src{buf0, C};
+    return run_sort(src, C, buf1, buf0, 0, rank_bits, w, false, 4.0 * (double)C, buf0, true);
 }
 
 uint64_t *expand_sort(const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,
