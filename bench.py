@@ -17,7 +17,6 @@ rate on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -43,29 +42,39 @@ WORKLOADS = {
 PAPER_PANCAKE12_SECONDS = 4923.0
 
 
-def kernel_source_digest() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2509_19162_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def stored_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, or None
-    when the kernel sources changed since the counters were taken."""
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    runs, or None when its device sources changed since the counters were
+    taken."""
+    from paper_2509_19162_amd.profiling import source_digest
+
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
     e = d.get(workload, {}).get(kernel)
-    if not e or e.get("source_digest") != kernel_source_digest():
+    if not e or e.get("source_digest") != source_digest(kernel):
         return None
     return e.get("bytes_per_launch")
+
+
+def calibrate_copy(nbytes: int, repeats: int) -> None:
+    """Runs the plain copy kernel `repeats` times over `nbytes` bytes: the
+    known traffic that scales the hardware counters."""
+    import torch
+
+    from paper_2509_19162_amd import testing
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    testing.copy(src, dst, repeats=repeats)
+    dt = time.perf_counter() - t
+    print(json.dumps({"copy_bytes": nbytes, "repeats": repeats,
+                      "gbs": round(2.0 * nbytes * repeats / dt / 1e9, 1)}), flush=True)
 
 
 def cpu_baseline(workload: dict, budget_s: float = 20.0):
@@ -270,6 +279,8 @@ def main():
     ap.add_argument("--ratios", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9, 1.0, 1.2])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run the plain copy kernel over BYTES bytes (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -284,6 +295,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        return calibrate_copy(args.calibrate_copy, max(1, args.steps))
     if args.workload == "batch4096":
         return bench_batch(args)
     if args.workload == "serving":
@@ -328,6 +341,7 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic,
+        "alg_bytes_per_launch": round(d["alg_bytes"] / d["launches"]),
         "avg_launch_ms": round(d["total_ms"] / d["launches"], 4),
         "launches": int(d["launches"]),
     }
@@ -352,7 +366,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": vs,
-        "dtype": "u64",
+        # candidates of n <= 12 are sorted and deduplicated as 32-bit ranks
+        "dtype": "u32" if n <= 12 else "u64",
         "data": "synthetic",
         "config": {
             "workload": wl["desc"],

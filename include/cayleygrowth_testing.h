@@ -86,6 +86,14 @@ int cg_test_unrank(int n, const uint32_t *h_ranks, uint64_t count, uint64_t *h_k
                    int on_device, void *stream);
 
 /*
+ * Plain device-to-device copy of `bytes` bytes (a multiple of 16, both
+ * pointers 16-byte aligned), run `repeats` times. Not part of the method:
+ * the known byte count calibrates hardware traffic counters against the
+ * kernels of the growth step.
+ */
+int cg_test_copy(const void *d_src, void *d_dst, uint64_t bytes, int repeats, void *stream);
+
+/*
  * Host emulation of the byte-permute expand (v_perm_b32 semantics written
  * out on the CPU): h_out[g*F + f] = key(s_f . g). Checks the selector
  * tables without a GPU.

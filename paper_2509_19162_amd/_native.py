@@ -127,6 +127,8 @@ SIGNATURES = [
     ("cg_test_unrank", ctypes.c_int,
      [ctypes.c_int, ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint64, u64p, ctypes.c_int, ctypes.c_void_p]),
     ("cg_test_host_expand", ctypes.c_int, [ctypes.c_int, u8p, ctypes.c_int, u64p, ctypes.c_uint64, u64p]),
+    ("cg_test_copy", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]),
     ("cg_test_layer_step", ctypes.c_int,
      [ctypes.c_int, u8p, ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
       ctypes.c_uint64, ctypes.c_void_p, u64p, ctypes.c_void_p]),

@@ -2,6 +2,7 @@
 // include/cayleygrowth_testing.h). Every entry point catches everything:
 // no C++ exception crosses the boundary; failures become CG_E_* codes with
 // a thread-local detail string.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -281,6 +282,14 @@ int cg_test_layer_step(int n, const uint8_t *h_gens, int k, const uint64_t *d_fr
 
 namespace {
 
+// Plain streaming copy, 16 bytes per lane per iteration: the reference for
+// what the HBM traffic counters read for a known byte count.
+__global__ __launch_bounds__(256) void copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                   uint64_t n16) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
 __global__ void rank_kernel(int n, const uint64_t *k, uint64_t count, uint32_t *r) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) r[i] = cg::perm_rank(k[i], n);
@@ -361,6 +370,25 @@ int cg_test_unrank(int n, const uint32_t *h_ranks, uint64_t count, uint64_t *h_k
                            a.as<uint32_t>(), count, b.as<uint64_t>());
         CG_HIP(hipGetLastError());
         CG_HIP(hipMemcpyAsync(h_keys, b.p, count * 8, hipMemcpyDeviceToHost, s));
+        CG_HIP(hipStreamSynchronize(s));
+        return CG_OK;
+    });
+}
+
+int cg_test_copy(const void *d_src, void *d_dst, uint64_t bytes, int repeats, void *stream) {
+    return guarded([&]() -> int {
+        if ((bytes & 15u) || repeats < 0 || (bytes && (!d_src || !d_dst)) ||
+            (((uintptr_t)d_src | (uintptr_t)d_dst) & 15u))
+            throw cg::Error(CG_E_INVAL, "copy needs 16-byte aligned buffers and a multiple of 16 bytes");
+        if (!bytes) return CG_OK;
+        hipStream_t s = (hipStream_t)stream;
+        const uint64_t n16 = bytes / 16;
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>((n16 + 255) / 256, 8192);
+        for (int r = 0; r < repeats; ++r) {
+            hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, s, (const uint4 *)d_src, (uint4 *)d_dst,
+                               n16);
+            CG_HIP(hipGetLastError());
+        }
         CG_HIP(hipStreamSynchronize(s));
         return CG_OK;
     });

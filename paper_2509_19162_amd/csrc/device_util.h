@@ -86,6 +86,10 @@ constexpr uint32_t kFlagAggregate = 1;
 constexpr uint32_t kFlagInclusive = 2;
 constexpr uint64_t kValueMask = (1ull << 46) - 1;
 constexpr uint32_t kSpinLimit = 1u << 24;
+#ifndef CG_LB_DEPTH
+#define CG_LB_DEPTH 4
+#endif
+constexpr int kLbDepth = CG_LB_DEPTH;  // predecessor words read per look-back round
 
 __device__ __forceinline__ uint64_t lb_word(uint32_t epoch, uint32_t flag, uint64_t v) {
     return ((uint64_t)epoch << 48) | ((uint64_t)flag << 46) | (v & kValueMask);
@@ -101,8 +105,8 @@ __device__ __forceinline__ uint64_t lb_load(const uint64_t *p) {
 }
 
 // Exclusive prefix of tile `tile` from the words of tiles tile-1, tile-2, ...
-// located at base[t * stride]; four predecessors are read per round so a
-// chain of aggregates costs a quarter of the round trips. Tiles publish in
+// located at base[t * stride]; kLbDepth predecessors are read per round so
+// a chain of aggregates costs fewer round trips. Tiles publish in
 // ticket order, so every tile waited on is already running; the wait is
 // still bounded: on overrun the error flag is raised and the (then
 // meaningless) partial sum returned.
@@ -114,14 +118,14 @@ __device__ __forceinline__ uint64_t lb_lookback(const uint64_t *base, uint64_t s
     uint32_t spins = 0;
     const uint64_t zero_incl = lb_word(epoch, kFlagInclusive, 0);
     while (t >= 0) {
-        uint64_t w[4];
+        uint64_t w[kLbDepth];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < kLbDepth; ++u)
             w[u] = (t - u >= 0) ? lb_load(base + (uint64_t)(t - u) * stride) : zero_incl;
         int used = 0;
         bool done = false;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kLbDepth; ++u) {
             if (done || used != u) break;
             if ((uint32_t)(w[u] >> 48) != epoch) break;
             excl += w[u] & kValueMask;

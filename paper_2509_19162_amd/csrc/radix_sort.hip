@@ -37,13 +37,20 @@ constexpr int kWaves = kBlock / kWave;
 // Keys per thread: 16 for 64-bit keys (4096-key tiles), 32 for 32-bit keys
 // (8192-key tiles). Both fill 32 KB of LDS per tile; the longer tiles of
 // 32-bit keys halve the per-tile fixed cost (look-back, digit scan).
+#ifndef CG_SORT_IPT32
+#define CG_SORT_IPT32 32
+#endif
 template <class K>
 struct TileOf {
-    static constexpr int ipt = sizeof(K) == 4 ? 32 : 16;
+    static constexpr int ipt = sizeof(K) == 4 ? CG_SORT_IPT32 : 16;
     static constexpr int tile = kBlock * ipt;
     static constexpr int wave_seg = kWave * ipt;  // keys owned by one wave
 };
 constexpr int kTile = TileOf<uint64_t>::tile;  // the shortest tile: sizes look-back state
+#ifndef CG_SORT_ROWS
+#define CG_SORT_ROWS 1
+#endif
+constexpr int kRows = CG_SORT_ROWS;  // rows ranked per LDS round trip
 
 static_assert(kBlock == kRadix, "one thread per digit in the look-back");
 
@@ -163,42 +170,57 @@ __global__ __launch_bounds__(kBlock) void hist_kernel(Src src, uint32_t ntiles, 
 }
 
 // ---- 1b. ranked expand with the histograms of every pass --------------------------
-// Each block takes a contiguous run of frontier states for one generator,
-// writes the candidates' 32-bit ranks (generator-major, out[g*F + f]) and
-// counts their digits for every pass (runs of equal digits per thread are
-// added with one LDS atomic), so the sort needs no separate histogram read.
+// Each block takes a contiguous run of frontier states; every state is read
+// once and mapped through all k generators, and the candidates' 32-bit
+// ranks go out generator-major (out[g*F + f], coalesced per generator).
+// The digits of every pass are counted on the way (runs of equal digits
+// per thread are added with one LDS atomic), so the sort needs no separate
+// histogram read.
+constexpr int kExpandIpt = 4;  // frontier states per thread and round
+
 template <int N>
 __global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
-    const uint64_t *__restrict__ frontier, uint64_t F, const GenSel *__restrict__ gsel,
-    uint32_t *__restrict__ out, uint32_t blocks_per_gen, PassDesc pd, unsigned long long *__restrict__ ghist) {
+    const uint64_t *__restrict__ frontier, uint64_t F, const GenSel *__restrict__ gsel, int k,
+    uint32_t *__restrict__ out, uint64_t per_block, PassDesc pd, unsigned long long *__restrict__ ghist) {
     __shared__ uint32_t s_h[kMaxPasses][kRadix];
     for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kBlock) (&s_h[0][0])[i] = 0;
     __syncthreads();
-    const uint32_t g = blockIdx.x / blocks_per_gen;
-    const uint64_t b = blockIdx.x - (uint64_t)g * blocks_per_gen;
-    const GenSel sel = gsel[g];
-    const uint64_t per = (F + blocks_per_gen - 1) / blocks_per_gen;  // contiguous share
-    const uint64_t lo = b * per;
-    const uint64_t hi = lo + per < F ? lo + per : F;
+    const uint64_t lo = (uint64_t)blockIdx.x * per_block;
+    const uint64_t hi = lo + per_block < F ? lo + per_block : F;
     uint32_t cur[kMaxPasses], run[kMaxPasses];
 #pragma unroll
     for (int p = 0; p < kMaxPasses; ++p) {
         cur[p] = 0;
         run[p] = 0;
     }
-    for (uint64_t f = lo + threadIdx.x; f < hi; f += kBlock) {
-        const uint32_t r = perm_rank_t<N>(apply_gensel(frontier[f], sel));
-        out[(uint64_t)g * F + f] = r;
+    for (uint64_t base = lo; base < hi; base += (uint64_t)kBlock * kExpandIpt) {
+        Nibbles st[kExpandIpt];
 #pragma unroll
-        for (int p = 0; p < kMaxPasses; ++p) {
-            if (p < pd.passes) {
-                const uint32_t d = (r >> pd.shift[p]) & pd.mask[p];
-                if (d != cur[p]) {
-                    if (run[p]) atomicAdd(&s_h[p][cur[p]], run[p]);
-                    cur[p] = d;
-                    run[p] = 1;
-                } else {
-                    ++run[p];
+        for (int j = 0; j < kExpandIpt; ++j) {
+            const uint64_t f = base + (uint64_t)j * kBlock + threadIdx.x;
+            st[j] = split_nibbles(f < hi ? frontier[f] : 0ull);
+        }
+        for (int g = 0; g < k; ++g) {
+            const GenSel sel = gsel[g];
+            uint32_t *o = out + (uint64_t)g * F;
+#pragma unroll
+            for (int j = 0; j < kExpandIpt; ++j) {
+                const uint64_t f = base + (uint64_t)j * kBlock + threadIdx.x;
+                if (f >= hi) continue;
+                const uint32_t r = perm_rank_t<N>(apply_gensel(st[j], sel));
+                o[f] = r;
+#pragma unroll
+                for (int p = 0; p < kMaxPasses; ++p) {
+                    if (p < pd.passes) {
+                        const uint32_t d = (r >> pd.shift[p]) & pd.mask[p];
+                        if (d != cur[p]) {
+                            if (run[p]) atomicAdd(&s_h[p][cur[p]], run[p]);
+                            cur[p] = d;
+                            run[p] = 1;
+                        } else {
+                            ++run[p];
+                        }
+                    }
                 }
             }
         }
@@ -232,8 +254,13 @@ __global__ void clear_kernel(unsigned long long *__restrict__ a, uint32_t na,
 }
 
 // ---- 3. one scatter pass -----------------------------------------------------------------
+#ifdef CG_SORT_WPE
+#define CG_SORT_ATTR __attribute__((amdgpu_waves_per_eu(CG_SORT_WPE)))
+#else
+#define CG_SORT_ATTR
+#endif
 template <class Src>
-__global__ __launch_bounds__(kBlock) void onesweep_kernel(
+__global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
     Src src, typename Src::Key *__restrict__ out, uint64_t total, int shift, uint32_t dmask,
     const unsigned long long *__restrict__ digit_base, uint64_t *__restrict__ status,
     uint32_t *__restrict__ ticket, uint32_t epoch, uint32_t *__restrict__ err) {
@@ -249,18 +276,18 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     __shared__ uint32_t s_tile;
 
     // the digit masks of the ranking live in s_keys until the scatter
-    uint64_t(*s_match)[kRadix] = reinterpret_cast<uint64_t(*)[kRadix]>(s_keys);
-    static_assert(kWaves * kRadix * sizeof(uint64_t) <= kTileK * sizeof(K), "match words fit in the key tile");
+    uint64_t(*s_match)[kWaves][kRadix] = reinterpret_cast<uint64_t(*)[kWaves][kRadix]>(s_keys);
+    static_assert(kRows * kWaves * kRadix * sizeof(uint64_t) <= kTileK * sizeof(K),
+                  "match words fit in the key tile");
+    static_assert(kIpt % kRows == 0, "rows per group divide the rows per thread");
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = tid / kWave;
 
     if (tid == 0) s_tile = atomicAdd(ticket, 1u);
-    for (int i = tid; i < kWaves * kRadix; i += kBlock) {
-        (&s_cnt[0][0])[i] = 0;
-        (&s_match[0][0])[i] = 0;
-    }
+    for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0;
+    for (int i = tid; i < kRows * kWaves * kRadix; i += kBlock) (&s_match[0][0][0])[i] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
     const auto T = src.tile(tile);
@@ -275,48 +302,62 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
         const uint32_t i = wave * kWaveSeg + j * kWave + lane;
         key[j] = i < nvalid ? T.get(i) : (K)kSentinel;
     }
-    // Peers (lanes of this wave holding the same digit) come from an LDS
-    // mask per digit: every lane ORs its lane bit into its digit's word,
-    // reads the word back and clears it. LDS instructions of one wave are
-    // processed in issue order, so every read sees all ORs of that row.
-    // A row whose valid lanes share one digit skips the LDS round trip.
-    uint32_t rank[kIpt];
+    // Peers (lanes of this wave holding the same digit) come from LDS masks:
+    // every lane ORs its lane bit into its digit's word, reads the words
+    // back and clears its own. Rows are ranked kRows at a time, each row with
+    // its own set of masks, so one LDS round trip serves kRows rows: a lane
+    // of row r reads the masks of all kRows rows at its digit, which gives
+    // the holders of that digit in earlier rows of the group and, for the
+    // digit's first holder, the group's count. LDS instructions of one wave
+    // are processed in issue order, so every read sees all ORs of its group
+    // and no clear overtakes a read.
+    uint32_t rank[kIpt];  // (rank within the wave's digit run) | digit << 16
+    static_assert(kTileK <= (1 << 16), "ranks fit in 16 bits");
 #pragma unroll
-    for (int j = 0; j < kIpt; ++j) {
-        const uint32_t i = wave * kWaveSeg + j * kWave + lane;
-        const bool valid = i < nvalid;
-        const uint32_t d = (uint32_t)(key[j] >> shift) & dmask;
-        const uint64_t vmask = __ballot(valid);
-        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-        uint64_t peers;
-#ifdef CG_SORT_MATCH_BALLOT
-        peers = vmask;
+    for (int j0 = 0; j0 < kIpt; j0 += kRows) {
+        uint32_t d[kRows];
+        bool valid[kRows];
 #pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
+        for (int r = 0; r < kRows; ++r) {
+            const uint32_t i = wave * kWaveSeg + (j0 + r) * kWave + lane;
+            valid[r] = i < nvalid;
+            d[r] = (uint32_t)(key[j0 + r] >> shift) & dmask;
         }
-        if (false) {
-#else
-        if (__ballot(valid && d == d0) == vmask) {
-#endif
-            peers = vmask;
-        } else {
-            if (valid) atomicOr(&s_match[wave][d], 1ull << lane);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            peers = valid ? s_match[wave][d] : 0ull;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            if (valid) s_match[wave][d] = 0ull;
+#pragma unroll
+        for (int r = 0; r < kRows; ++r)
+            if (valid[r]) atomicOr(&s_match[r][wave][d[r]], 1ull << lane);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        uint64_t m[kRows][kRows];
+        uint32_t old[kRows];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+#pragma unroll
+            for (int q = 0; q < kRows; ++q) m[r][q] = valid[r] ? s_match[q][wave][d[r]] : 0ull;
+            old[r] = valid[r] ? s_cnt[wave][d[r]] : 0u;
         }
-        const uint32_t below = mask_rank(peers);
-        const uint32_t cnt = (uint32_t)__popcll(peers);
-        uint32_t old = 0;
-        if (valid) old = s_cnt[wave][d];
-        if (valid && below == 0) s_cnt[wave][d] = old + cnt;
-        rank[j] = old + below;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int r = 0; r < kRows; ++r)
+            if (valid[r]) s_match[r][wave][d[r]] = 0ull;
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            uint32_t before = mask_rank(m[r][r]);
+            uint32_t total = 0;
+            bool first = before == 0;
+#pragma unroll
+            for (int q = 0; q < kRows; ++q) {
+                const uint32_t c = (uint32_t)__popcll(m[r][q]);
+                total += c;
+                if (q < r) {
+                    before += c;
+                    first = first && c == 0;
+                }
+            }
+            rank[j0 + r] = (old[r] + before) | (d[r] << 16);  // rank < 2^16 beside the digit
+            if (valid[r] && first) s_cnt[wave][d[r]] = old[r] + total;
+        }
     }
     __syncthreads();
 
@@ -349,8 +390,8 @@ __global__ __launch_bounds__(kBlock) void onesweep_kernel(
     for (int j = 0; j < kIpt; ++j) {
         const uint32_t i = wave * kWaveSeg + j * kWave + lane;
         if (i < nvalid) {
-            const uint32_t d = (uint32_t)(key[j] >> shift) & dmask;
-            s_keys[s_lstart[d] + s_cnt[wave][d] + rank[j]] = key[j];
+            const uint32_t d = rank[j] >> 16;
+            s_keys[s_lstart[d] + s_cnt[wave][d] + (rank[j] & 0xFFFFu)] = key[j];
         }
     }
     __syncthreads();
@@ -510,15 +551,16 @@ uint32_t *expand_rank_sort(int n, const uint64_t *frontier, uint64_t F, const Ge
                        w.tickets(), 32u);
     CG_HIP(hipGetLastError());
     if (w.prof) w.prof->end(K_AUX, 0, 0);
-    uint64_t per = (F + kBlock - 1) / kBlock;
-    uint64_t want = (2048 + (uint64_t)k - 1) / (uint64_t)k;
-    if (want < 8) want = 8;
-    uint32_t bpg = (uint32_t)(per < want ? per : want);
-    if (bpg == 0) bpg = 1;
+    // rounds of kBlock*kExpandIpt states; at most 4096 blocks
+    const uint64_t round = (uint64_t)kBlock * kExpandIpt;
+    const uint64_t rounds = (F + round - 1) / round;
+    const uint64_t blocks = rounds < 4096 ? rounds : 4096;
+    const uint64_t per_block = ((rounds + blocks - 1) / blocks) * round;
+    const uint32_t grid = (uint32_t)((F + per_block - 1) / per_block);
     if (w.prof) w.prof->begin(K_EXPAND);
     with_rank_n(n, [&](auto NN) {
-        hipLaunchKernelGGL(expand_rank_hist_kernel<decltype(NN)::value>, dim3(bpg * (uint32_t)k), dim3(kBlock), 0,
-                           w.stream, frontier, F, d_gsel, buf0, bpg, pd, hist);
+        hipLaunchKernelGGL(expand_rank_hist_kernel<decltype(NN)::value>, dim3(grid), dim3(kBlock), 0, w.stream,
+                           frontier, F, d_gsel, k, buf0, per_block, pd, hist);
     });
     CG_HIP(hipGetLastError());
     if (w.prof) w.prof->end(K_EXPAND, 8.0 * (double)F + 4.0 * (double)C, (double)C);

@@ -80,6 +80,14 @@ def layer_step(n: int, gens, frontier, prev, stream=None):
     return out[: cnt.value]
 
 
+def copy(src, dst, repeats: int = 1, stream=None):
+    """Plain device copy of src into dst (same byte size, a multiple of 16)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("copy needs buffers of the same byte size")
+    _check(N.lib().cg_test_copy(_dptr(src), _dptr(dst), nbytes, repeats, _stream(stream)))
+
+
 def to_u64(t) -> np.ndarray:
     """Copy a device int64 key tensor to host uint64."""
     return t.cpu().numpy().view(np.uint64)

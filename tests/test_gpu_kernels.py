@@ -122,3 +122,12 @@ def test_layer_steps_reproduce_coxeter_layers():
         assert np.array_equal(T.to_u64(out), layers[d]), d
         p, f = f, out
     assert T.layer_step(n, gens, f, p).numel() == 0
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 16 * 7, 1 << 22])
+def test_copy_kernel_copies(nbytes, rng):
+    src = torch.from_numpy(rng.integers(0, 256, nbytes, dtype=np.uint8)).cuda()
+    dst = torch.zeros_like(src)
+    T.copy(src, dst, repeats=2)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
