@@ -69,6 +69,16 @@ extern "C" {
 #define CG_PACKED_SORT 0x10u     /* sort candidates as packed 64-bit keys
                                     even when n <= 12 (by default they sort
                                     as 32-bit lexicographic ranks there)     */
+#define CG_BITMASK 0x20u         /* run the bitmask engine instead of the
+                                    sort-based one: three bitmaps over the
+                                    n! lexicographic ranks (visited, layer d,
+                                    layer d+1: 3 bits per state, the
+                                    memory-saving encoding of the paper's
+                                    section on growth benchmarks). n <= 14,
+                                    start state a permutation, no layer
+                                    export; n! * 3/8 bytes of device memory
+                                    (32.7 GB at n = 14). Exact; directed
+                                    sets allowed with CG_ALLOW_DIRECTED.     */
 
 /*
  * A growth job.

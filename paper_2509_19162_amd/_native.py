@@ -29,6 +29,7 @@ CG_ALLOW_DIRECTED = 0x2
 CG_START_STATE = 0x4
 CG_PROFILE = 0x8
 CG_PACKED_SORT = 0x10
+CG_BITMASK = 0x20
 
 CG_KSTAT_MAX = 8
 

@@ -136,8 +136,10 @@ def growth(n: int, gens: Sequence[Sequence[int]], max_layers: int = 256,
 def growth_ex(n: int, gens: Sequence[Sequence[int]], max_layers: int = 256,
               max_frontier: Optional[int] = None, start: Optional[Sequence[int]] = None,
               keep_all_layers: bool = False, allow_directed: bool = False, profile: bool = False,
-              export_layers: int = 0, stream=None, packed_sort: bool = False) -> GrowthResult:
-    """The full job interface (``cg_growth_ex``).
+              export_layers: int = 0, stream=None, packed_sort: bool = False,
+              bitmask: bool = False) -> GrowthResult:
+    """The full job interface (``cg_growth_ex``). ``bitmask`` selects the
+    rank-space bitmap engine (n <= 14, sizes only).
 
     ``export_layers``: capacity (in states) of the layer-content export; the
     result's ``layers`` then lists each layer's states in increasing
@@ -152,6 +154,8 @@ def growth_ex(n: int, gens: Sequence[Sequence[int]], max_layers: int = 256,
         flags |= N.CG_PROFILE
     if packed_sort:
         flags |= N.CG_PACKED_SORT
+    if bitmask:
+        flags |= N.CG_BITMASK
     h = _JobHolder(n, gens, max_layers, max_frontier, flags, start, export_layers)
     _check(N.lib().cg_growth_ex(ctypes.byref(h.job), ctypes.byref(h.res), _stream_handle(stream)))
     return h.result()
@@ -168,10 +172,11 @@ class Engine:
 
     def run(self, n: int, gens, max_layers: int = 256, max_frontier: Optional[int] = None,
             start=None, keep_all_layers: bool = False, allow_directed: bool = False,
-            profile: bool = False, export_layers: int = 0, packed_sort: bool = False) -> GrowthResult:
+            profile: bool = False, export_layers: int = 0, packed_sort: bool = False,
+            bitmask: bool = False) -> GrowthResult:
         flags = (N.CG_KEEP_ALL_LAYERS if keep_all_layers else 0) | \
                 (N.CG_ALLOW_DIRECTED if allow_directed else 0) | (N.CG_PROFILE if profile else 0) | \
-                (N.CG_PACKED_SORT if packed_sort else 0)
+                (N.CG_PACKED_SORT if packed_sort else 0) | (N.CG_BITMASK if bitmask else 0)
         h = _JobHolder(n, gens, max_layers, max_frontier, flags, start, export_layers)
         _check(N.lib().cg_engine_run(self._e, ctypes.byref(h.job), ctypes.byref(h.res)))
         return h.result()
@@ -189,7 +194,7 @@ class Engine:
 
 
 def growth_batch(jobs, max_layers: int = 256, max_active: int = 0, budget_bytes: int = 0,
-                 tune: bool = True, stream=None) -> List[GrowthResult]:
+                 tune: bool = False, stream=None, allow_directed: bool = False) -> List[GrowthResult]:
     """Many independent jobs in shared super-steps (``cg_growth_batch``).
 
     ``jobs``: a list of ``(n, gens)``, ``(n, gens, max_frontier)`` or
@@ -201,7 +206,7 @@ def growth_batch(jobs, max_layers: int = 256, max_active: int = 0, budget_bytes:
         n, gens = j[0], j[1]
         mf = j[2] if len(j) > 2 else None
         ml = j[3] if len(j) > 3 and j[3] else max_layers
-        holders.append(_JobHolder(n, gens, ml, mf, 0, None, 0))
+        holders.append(_JobHolder(n, gens, ml, mf, N.CG_ALLOW_DIRECTED if allow_directed else 0, None, 0))
     JobArr = N.CgJob * len(holders)
     ResArr = N.CgResult * len(holders)
     ja = JobArr(*[h.job for h in holders])

@@ -9,6 +9,11 @@
 // tags keep the jobs' states apart.
 #include "batch.h"
 
+#include <cstdlib>
+#include <mutex>
+
+#include "bitmap.h"
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -243,8 +248,77 @@ void BatchGroup::step(std::vector<int> &finished) {
 
 namespace cg {
 
-// Groups of the batch: jobs of one n share a group (a size class), at most
-// `cap` jobs per group.
+// Size classes of a batch are the job's n. Per class the batch picks an
+// engine: the small-job engine (one workgroup per job, every such job of
+// the batch in one persistent launch captured as a hipGraph) or tagged
+// super-step groups of at most `cap` jobs. The default: small-job engine up
+// to n = wg_max_n (CG_WG_MAX_N, default 10); with opts->tune the autotuner
+// times both engines on a sample of each class and keeps the faster, and
+// picks the workgroup size. Results are exact either way.
+namespace {
+
+int default_wg_max_n() {
+    const char *e = std::getenv("CG_WG_MAX_N");
+    if (!e) return kWgMaxN;
+    return std::max(0, std::min(kWgMaxN, std::atoi(e)));
+}
+
+struct ClassChoice {
+    bool wg = false;
+    WgTuning tuning;
+};
+
+double time_groups(std::vector<std::pair<JobSpec, cg_result_t *>> &sample, int n, hipStream_t stream) {
+    const double t = now_seconds();
+    BatchGroup g(stream, n, (int)sample.size());
+    for (int j = 0; j < (int)sample.size(); ++j) g.add(j, sample[j].first, sample[j].second, t, t);
+    std::vector<int> fin;
+    while (!g.idle()) g.step(fin);
+    CG_HIP(hipStreamSynchronize(stream));
+    return now_seconds() - t;
+}
+
+// Times both engines on up to 256 jobs of the class (cached per device and
+// n for the process).
+ClassChoice tune_class(int n, std::vector<std::pair<JobSpec, cg_result_t *>> &items, hipStream_t stream) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, ClassChoice> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto f = cache.find({dev, n});
+        if (f != cache.end()) return f->second;
+    }
+    const size_t m = std::min<size_t>(256, items.size());
+    std::vector<std::pair<JobSpec, cg_result_t *>> sample;
+    std::vector<std::vector<uint64_t>> sizes(m);
+    std::vector<cg_result_t> res(m);
+    for (size_t i = 0; i < m; ++i) {
+        sizes[i].assign((size_t)items[i].first.max_layers, 0);
+        std::memset(&res[i], 0, sizeof(cg_result_t));
+        res[i].layer_sizes = sizes[i].data();
+        sample.push_back({items[i].first, &res[i]});
+    }
+    std::vector<WgItem> wi;
+    for (auto &x : sample) wi.push_back({&x.first, x.second});
+    ClassChoice c;
+    c.tuning = tune_wg(wi, stream);
+    WgRunner r(stream);
+    r.run(wi, c.tuning, now_seconds());
+    double t = now_seconds();
+    r.run(wi, c.tuning, t);
+    const double wg_s = now_seconds() - t;
+    (void)time_groups(sample, n, stream);  // warm-up (allocations)
+    const double grp_s = time_groups(sample, n, stream);
+    c.wg = wg_s <= grp_s;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[{dev, n}] = c;
+    return c;
+}
+
+}  // namespace
+
 void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_batch_opts_t *opts) {
     const double t0 = now_seconds();
     hipStream_t stream = opts ? (hipStream_t)opts->stream : nullptr;
@@ -272,10 +346,53 @@ void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_
             r->num_layers = 0;
         }
     }
+    const bool tune = opts && opts->tune;
+    const int wg_max_n = default_wg_max_n();
     try {
+        std::vector<WgItem> wg_items;
+        WgTuning wg_t;
+        int wg_t_n = -1;
         for (auto &kv : by_n) {
             const int n = kv.first;
-            auto &items = kv.second;
+            auto &all = kv.second;
+            // jobs the small-job engine cannot take stay in groups; groups
+            // need closure under inverses
+            std::vector<Item> items;
+            std::vector<Item *> wg_ok;
+            for (auto &it : all) {
+                if (wg_eligible(it.spec))
+                    wg_ok.push_back(&it);
+                else if (!it.spec.inverse_closed) {
+                    cg_result_t *r = &results[it.idx];
+                    r->status = CG_E_UNSUPPORTED;
+                    r->num_layers = 0;
+                } else
+                    items.push_back(it);
+            }
+            if (!wg_ok.empty()) {
+                ClassChoice c;
+                c.wg = n <= wg_max_n;
+                bool all_closed = true;
+                for (Item *it : wg_ok) all_closed = all_closed && it->spec.inverse_closed;
+                if (tune && all_closed) {
+                    std::vector<std::pair<JobSpec, cg_result_t *>> cls;
+                    for (Item *it : wg_ok) cls.push_back({it->spec, &results[it->idx]});
+                    c = tune_class(n, cls, stream);
+                }
+                if (!all_closed) c.wg = true;  // only this engine takes directed sets
+                for (Item *it : wg_ok) {
+                    if (c.wg) {
+                        wg_items.push_back({&it->spec, &results[it->idx]});
+                        if (n > wg_t_n) {
+                            wg_t_n = n;
+                            wg_t = c.tuning;
+                        }
+                    } else if (it->spec.inverse_closed) {
+                        items.push_back(*it);
+                    }
+                }
+            }
+            if (items.empty()) continue;
             int cap = 1;
             while (4 * n + 1 + (int)std::log2((double)cap) <= 64 && cap < 4096) cap <<= 1;
             if (4 * n >= 64) cap = 1;
@@ -304,6 +421,11 @@ void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_
                     todo.push_back({span.first, (size_t)m / 2});
                 }
             }
+        }
+        if (!wg_items.empty()) {
+            // one persistent launch for every small job of the batch
+            WgRunner r(stream);
+            r.run(wg_items, wg_t, t0);
         }
     } catch (...) {
         if (own) {

@@ -12,6 +12,7 @@
 // The loop stops at an empty layer (complete), after max_layers layers, or
 // after recording the first layer larger than max_frontier (truncated).
 #include "engine.h"
+#include "bitmap.h"
 
 #include "perm_rank.h"
 
@@ -37,8 +38,7 @@ JobSpec canonicalize(const cg_job_t &job, bool batch) {
     s.max_layers = job.max_layers;
     s.max_frontier = job.max_frontier;
     s.flags = job.flags;
-    if (batch && (job.flags & (CG_ALLOW_DIRECTED | CG_KEEP_ALL_LAYERS)))
-        throw Error(CG_E_INVAL, "batched jobs cannot keep all layers or be directed");
+    if (batch && (job.flags & CG_KEEP_ALL_LAYERS)) throw Error(CG_E_INVAL, "batched jobs cannot keep all layers");
     if (batch && job.layers_out) throw Error(CG_E_INVAL, "batched jobs cannot export layers");
     s.layers_out = job.layers_out;
     s.layers_out_cap = job.layers_out ? job.layers_out_cap : 0;
@@ -186,6 +186,10 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
     }
     w_.prof = prof_.on ? &prof_ : nullptr;
 
+    if (spec.flags & CG_BITMASK) {
+        run_bitmask(spec, res, stream_);
+        return;
+    }
     const int n = spec.n, k = spec.k;
     const bool keep_all = (spec.flags & CG_KEEP_ALL_LAYERS) != 0;
     const bool directed = !spec.inverse_closed;

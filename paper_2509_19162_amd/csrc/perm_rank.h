@@ -3,7 +3,8 @@
 // smaller than s[i] that do not occur before position i (the Lehmer code);
 // it is a bijection from S_n onto [0, n!) that preserves order, so sorting
 // ranks sorts the keys. Used for n <= 12 (12! < 2^32) to sort and compare
-// candidates as 32-bit words while layers stay packed 64-bit keys.
+// candidates as 32-bit words while layers stay packed 64-bit keys, and as
+// the bit index of the rank-space bitmaps.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -48,27 +49,29 @@ __host__ __device__ __forceinline__ uint64_t perm_unrank(uint32_t rank, int n) {
 }
 
 // The same with n fixed at compile time: the loops unroll, shifts become
-// constants and the divisions of the unrank become multiplications.
-template <int N>
-__host__ __device__ __forceinline__ uint32_t perm_rank_t(uint64_t key) {
-    uint32_t rank = 0, used = 0;
+// constants and the divisions of the unrank become multiplications. R is
+// the rank type: uint32_t up to n = 12, uint64_t beyond (16! < 2^45).
+template <int N, class R = uint32_t>
+__host__ __device__ __forceinline__ R perm_rank_t(uint64_t key) {
+    R rank = 0;
+    uint32_t used = 0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         const uint32_t v = (uint32_t)(key >> (4 * (N - 1 - i))) & 15u;
         const uint32_t c = v - (uint32_t)__builtin_popcount(used & ((1u << v) - 1u));
-        rank = rank * (uint32_t)(N - i) + c;
+        rank = rank * (R)(N - i) + (R)c;
         used |= 1u << v;
     }
     return rank;
 }
 
-template <int N>
-__host__ __device__ __forceinline__ uint64_t perm_unrank_t(uint32_t rank) {
+template <int N, class R = uint32_t>
+__host__ __device__ __forceinline__ uint64_t perm_unrank_t(R rank) {
     uint32_t c[N > 0 ? N : 1];
 #pragma unroll
     for (int i = N - 1; i >= 0; --i) {
-        c[i] = rank % (uint32_t)(N - i);
-        rank /= (uint32_t)(N - i);
+        c[i] = (uint32_t)(rank % (R)(N - i));
+        rank /= (R)(N - i);
     }
     uint64_t avail = 0;
 #pragma unroll
