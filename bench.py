@@ -35,6 +35,12 @@ WORKLOADS = {
                      desc="S_8, 7 adjacent transpositions (bubble-sort graph), full BFS"),
     "lrx16": dict(n=16, family="lrx", keep_all=False, max_frontier=1 << 31,
                   desc="S_16, LRX, layers up to the first one larger than 2^31"),
+    # the bitmask engine (3 bits per state over the n! ranks) on groups the
+    # sort path cannot hold
+    "pancake13": dict(n=13, family="pancake", keep_all=False, max_frontier=None, bitmask=True,
+                      desc="S_13, 12 prefix reversals (pancake), full BFS, bitmask engine"),
+    "coxeter14": dict(n=14, family="coxeter", keep_all=False, max_frontier=None, bitmask=True,
+                      desc="S_14, 13 adjacent transpositions, full BFS, bitmask engine"),
 }
 
 # Paper, table "Growth computations ... CPU on Kaggle cloud" (timing table
@@ -306,21 +312,23 @@ def main():
     gens = I.family(wl["family"], n)
     stream = torch.cuda.Stream()
     eng = api.Engine(stream=stream)
-    run_kw = dict(max_layers=512, keep_all_layers=wl["keep_all"], max_frontier=wl["max_frontier"])
+    bitmask = wl.get("bitmask", False)
+    run_kw = dict(max_layers=512, keep_all_layers=wl["keep_all"], max_frontier=wl["max_frontier"],
+                  bitmask=bitmask)
 
     for _ in range(args.warmup):
         eng.run(n, gens, **run_kw)
     torch.cuda.synchronize()
 
     t0 = time.perf_counter()
-    results = [eng.run(n, gens, profile=True, **run_kw) for _ in range(args.steps)]
+    results = [eng.run(n, gens, profile=not bitmask, **run_kw) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
 
     sizes = results[0].sizes
     for r in results[1:]:
         assert r.sizes == sizes, "growth differs between steps"
-    if wl["family"] == "pancake" and wl["max_frontier"] is None:
+    if wl["family"] in ("pancake", "coxeter") and wl["max_frontier"] is None:
         assert sum(sizes) == math.factorial(n), "layer sizes do not sum to n!"
     expanded = results[0].states_expanded
     elapsed = t1 - t0
@@ -328,24 +336,45 @@ def main():
     value = expanded * args.steps / elapsed
 
     # dominant kernel over the timed region
+    roofline = None
+    kernel_ms = None
     agg = agg_kstats(results)
-    dom = max(agg, key=lambda k: agg[k]["total_ms"])
-    d = agg[dom]
-    achieved = d["alg_bytes"] / (d["total_ms"] / 1000.0) / 1e9
-    traffic = stored_traffic(dom, args.workload)
-    roofline = {
-        "bound": "hbm",
-        "kernel": dom,
-        "achieved": round(achieved, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": traffic,
-        "alg_bytes_per_launch": round(d["alg_bytes"] / d["launches"]),
-        "avg_launch_ms": round(d["total_ms"] / d["launches"], 4),
-        "launches": int(d["launches"]),
-    }
-    kernel_ms = {k: round(v["total_ms"] / args.steps, 3) for k, v in sorted(agg.items())}
+    if agg:
+        dom = max(agg, key=lambda k: agg[k]["total_ms"])
+        d = agg[dom]
+        achieved = d["alg_bytes"] / (d["total_ms"] / 1000.0) / 1e9
+        traffic = stored_traffic(dom, args.workload)
+        roofline = {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "alg_bytes_per_launch": round(d["alg_bytes"] / d["launches"]),
+            "avg_launch_ms": round(d["total_ms"] / d["launches"], 4),
+            "launches": int(d["launches"]),
+        }
+        kernel_ms = {k: round(v["total_ms"] / args.steps, 3) for k, v in sorted(agg.items())}
+
+    # the same job as one workgroup-resident launch (a replayed hipGraph)
+    graph_variant = None
+    if n <= 10 and not bitmask:
+        geng = api.Engine(stream=stream)
+        for _ in range(3):
+            geng.run(n, gens, max_layers=512, small_job=True)
+        torch.cuda.synchronize()
+        reps = max(20, args.steps)
+        tg = time.perf_counter()
+        for _ in range(reps):
+            rg = geng.run(n, gens, max_layers=512, small_job=True)
+        torch.cuda.synchronize()
+        g_ms = 1000.0 * (time.perf_counter() - tg) / reps
+        assert rg.sizes == sizes, "small-job engine differs from the sort path"
+        graph_variant = {"ms_per_run": round(g_ms, 3), "device_ms": round(rg.device_ms, 3),
+                         "speedup_vs_plain": round(ms_per_step / g_ms, 1)}
+        geng.close()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -367,7 +396,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": vs,
         # candidates of n <= 12 are sorted and deduplicated as 32-bit ranks
-        "dtype": "u32" if n <= 12 else "u64",
+        "dtype": "u32" if n <= 12 else "u64",  # bitmask engine: u32 bitmap words, u64 ranks above n = 12
         "data": "synthetic",
         "config": {
             "workload": wl["desc"],
@@ -381,6 +410,10 @@ def main():
         "cpu_baseline": cpu,
         "kernel_ms_per_step": kernel_ms,
     }
+    if graph_variant:
+        line["graph_variant"] = graph_variant
+    if bitmask:
+        line["engine"] = "bitmask (3 bits per state; VALU and atomic bound, no HBM roofline)"
     if vs is not None:
         line["baseline_note"] = ("paper: S_12 pancake full growth 4923 s on a Kaggle CPU "
                                  "(another machine; context only)")

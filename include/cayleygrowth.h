@@ -79,6 +79,12 @@ extern "C" {
                                     export; n! * 3/8 bytes of device memory
                                     (32.7 GB at n = 14). Exact; directed
                                     sets allowed with CG_ALLOW_DIRECTED.     */
+#define CG_SMALL_JOB 0x40u       /* run the whole job inside one workgroup
+                                    (n <= 10, start a permutation, no layer
+                                    export): one launch, rank-space bitmaps
+                                    in LDS or a device slot; on a reusable
+                                    engine the launch is a hipGraph that is
+                                    replayed while the job's shape repeats */
 
 /*
  * A growth job.

@@ -30,6 +30,7 @@ CG_START_STATE = 0x4
 CG_PROFILE = 0x8
 CG_PACKED_SORT = 0x10
 CG_BITMASK = 0x20
+CG_SMALL_JOB = 0x40
 
 CG_KSTAT_MAX = 8
 

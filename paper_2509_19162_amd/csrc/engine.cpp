@@ -116,6 +116,7 @@ Engine::Engine(hipStream_t user_stream) {
 }
 
 Engine::~Engine() {
+    delete wg_;
     if (host_small_) (void)hipHostFree(host_small_);
     // buffers go back to the device cache while their stream still exists
     for (DevBuf *b : {&gsel_, &cand0_, &cand1_, &lay_[0], &lay_[1], &lay_[2], &arena_, &stage_}) b->release();
@@ -188,6 +189,17 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
 
     if (spec.flags & CG_BITMASK) {
         run_bitmask(spec, res, stream_);
+        return;
+    }
+    if (spec.flags & CG_SMALL_JOB) {
+        if (!wg_eligible(spec))
+            throw Error(CG_E_INVAL, "CG_SMALL_JOB needs n <= 10, a permutation start, at most 128 generators "
+                                    "and no layer export");
+        if (!wg_) wg_ = new WgRunner(stream_);
+        std::vector<WgItem> one{{&spec, res}};
+        WgTuning t;
+        t.block = 256;
+        wg_->run(one, t, t0);
         return;
     }
     const int n = spec.n, k = spec.k;

@@ -56,6 +56,7 @@ private:
     PipeWork w_;
     Profiler prof_;
     DevBuf gsel_, cand0_, cand1_, lay_[3], arena_, stage_;
+    class WgRunner *wg_ = nullptr;  // small-job engine (created on first use)
     uint64_t *host_small_ = nullptr;  // pinned: counter + error flag
 };
 

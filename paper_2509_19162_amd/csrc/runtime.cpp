@@ -25,11 +25,10 @@ void hip_check(hipError_t e, const char *what, const char *file, int line) {
 // held, but a large one takes seconds once tens of GB are already held. So
 // the first large request reserves one big region (CG_ARENA_FRACTION of the
 // free memory, default 0.85; 0 disables it) and every buffer is carved out
-// of it: best fit, split on allocation, coalesced on free. A freed range
-// carries an event recorded on its owner's stream and is reused only once
-// the event has completed, so work still queued on the old stream never
-// races with a new owner. Requests the arena cannot hold fall back to plain
-// hipMalloc/hipFree.
+// of it: best fit, split on allocation, coalesced on free. A range is
+// freed only after its owner's stream has drained, so work still queued on
+// the old stream never races with a new owner. Requests the arena cannot
+// hold fall back to plain hipMalloc/hipFree.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -42,11 +41,6 @@ struct Arena {
     bool tried = false;
     std::map<size_t, size_t> by_off;            // free ranges: offset -> length
     std::multimap<size_t, size_t> by_len;       // free ranges: length -> offset
-    struct Pending {
-        size_t off, len;
-        hipEvent_t ev;
-    };
-    std::vector<Pending> pending;
     size_t used = 0;
 
     void insert_free(size_t off, size_t len) {
@@ -76,48 +70,16 @@ struct Arena {
                 return;
             }
     }
-    void reclaim(bool wait) {
-        std::vector<Pending> keep;
-        for (auto &p : pending) {
-            bool done = true;
-            if (p.ev) {
-                if (wait) {
-                    (void)hipEventSynchronize(p.ev);
-                } else {
-                    const hipError_t q = hipEventQuery(p.ev);
-                    if (q == hipErrorNotReady) {
-                        done = false;
-                    } else if (q != hipSuccess) {
-                        (void)hipGetLastError();
-                        (void)hipEventSynchronize(p.ev);
-                    }
-                }
-            }
-            if (done) {
-                if (p.ev) (void)hipEventDestroy(p.ev);
-                insert_free(p.off, p.len);
-            } else {
-                keep.push_back(p);
-            }
-        }
-        pending.swap(keep);
-    }
     bool take(size_t len, size_t &off) {
-        for (int pass = 0; pass < 2; ++pass) {
-            reclaim(pass == 1);
-            auto it = by_len.lower_bound(len);
-            if (it != by_len.end()) {
-                const size_t flen = it->first, foff = it->second;
-                by_len.erase(it);
-                by_off.erase(foff);
-                if (flen > len) insert_free(foff + len, flen - len);
-                off = foff;
-                used += len;
-                return true;
-            }
-            if (pending.empty()) break;
-        }
-        return false;
+        auto it = by_len.lower_bound(len);
+        if (it == by_len.end()) return false;
+        const size_t flen = it->first, foff = it->second;
+        by_len.erase(it);
+        by_off.erase(foff);
+        if (flen > len) insert_free(foff + len, flen - len);
+        off = foff;
+        used += len;
+        return true;
     }
 };
 
@@ -169,14 +131,14 @@ void *arena_alloc(int dev, size_t len) {
     return A.base + off;
 }
 
-bool arena_free(int dev, void *p, size_t len, hipEvent_t ev) {
+bool arena_free(int dev, void *p, size_t len) {
     std::lock_guard<std::mutex> lk(arenas().mu);
     auto it = arenas().arena.find(dev);
     if (it == arenas().arena.end() || !it->second.base) return false;
     Arena &A = it->second;
     char *c = (char *)p;
     if (c < A.base || c >= A.base + A.size) return false;
-    A.pending.push_back({(size_t)(c - A.base), len, ev});
+    A.insert_free((size_t)(c - A.base), len);
     A.used -= len;
     return true;
 }
@@ -188,7 +150,6 @@ void release_cached_device_memory() {
     for (auto &kv : arenas().arena) {
         Arena &A = kv.second;
         if (!A.base || A.used) continue;  // ranges still handed out
-        A.reclaim(true);
         (void)hipFree(A.base);
         A = Arena{};
     }
@@ -237,20 +198,14 @@ bool DevBuf::ensure(size_t need, double slack) {
 void DevBuf::release() {
     if (p) {
         if (in_arena) {
-            hipEvent_t ev = nullptr;
-            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
-                if (hipEventRecord(ev, stream) != hipSuccess) {
-                    (void)hipGetLastError();
-                    (void)hipEventDestroy(ev);
-                    ev = nullptr;
-                    (void)hipDeviceSynchronize();
-                }
-            } else {
+            // Work still queued on the owner stream may use the range: wait
+            // for it, then hand the range back. (No event is kept for later:
+            // the owner stream may be destroyed before anyone would query it.)
+            if (hipStreamSynchronize(stream) != hipSuccess) {
                 (void)hipGetLastError();
-                ev = nullptr;
                 (void)hipDeviceSynchronize();
             }
-            if (!arena_free(dev, p, bytes, ev) && ev) (void)hipEventDestroy(ev);
+            (void)arena_free(dev, p, bytes);
         } else {
             (void)hipFree(p);  // a block of its own; synchronises the device
         }

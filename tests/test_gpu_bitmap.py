@@ -201,3 +201,24 @@ def test_small_job_engine_repeat_and_tuned(wg_max_n, oracle_c):
     for tune in (False, False, True):
         res = api.growth_batch(jobs, max_layers=512, tune=tune)
         assert [r.sizes for r in res] == exp
+
+
+def test_small_job_flag_on_engine_replays_graph(oracle_c):
+    eng = api.Engine()
+    for n, fam in [(8, "coxeter"), (8, "coxeter"), (9, "pancake"), (7, "lrx"), (8, "coxeter")]:
+        gens = I.family(fam, n)
+        r = eng.run(n, gens, max_layers=512, small_job=True)
+        exp, rc, _ = oracle_c.growth(n, gens, max_layers=512)
+        assert r.status == rc and r.sizes == exp
+    r = eng.run(8, I.coxeter(8), max_layers=5, small_job=True)
+    assert r.status == N.CG_TRUNCATED and r.sizes == oracle_c.growth(8, I.coxeter(8), max_layers=5)[0]
+    with pytest.raises(api.CGError):
+        eng.run(11, I.coxeter(11), small_job=True)
+    eng.close()
+
+
+def test_bitmask_full_s14_coxeter_is_mahonian():
+    # the whole of S_14 (8.7e10 states, 92 layers) on one device: about 30 s
+    r = api.growth_ex(14, I.coxeter(14), max_layers=128, bitmask=True)
+    assert r.status == N.CG_OK
+    assert r.sizes == mahonian(14)
