@@ -17,6 +17,8 @@
 #include "perm_rank.h"
 
 #include <algorithm>
+#include <cstdlib>
+#include <memory>
 #include <chrono>
 #include <cstdio>
 #include <cstring>
@@ -119,7 +121,8 @@ Engine::~Engine() {
     delete wg_;
     if (host_small_) (void)hipHostFree(host_small_);
     // buffers go back to the device cache while their stream still exists
-    for (DevBuf *b : {&gsel_, &cand0_, &cand1_, &lay_[0], &lay_[1], &lay_[2], &arena_, &stage_}) b->release();
+    for (DevBuf *b : {&gsel_, &cand0_, &cand1_, &lay_[0], &lay_[1], &lay_[2], &arena_, &stage_, &chunk_hist_})
+        b->release();
     for (DevBuf *b : {&w_.hist, &w_.base, &w_.small, &w_.status, &w_.bounds, &w_.tile_cnt, &w_.tile_off,
                       &w_.kill})
         b->release();
@@ -166,6 +169,110 @@ void fill_kstats(const Profiler &p, cg_result_t *res) {
         s.alg_bytes = p.bytes[k];
         s.items = p.items[k];
     }
+}
+
+// Candidates one layer may hold at once: all of them when two candidate
+// arrays plus the new layer fit in the free device memory, else a chunk of
+// that size (CG_CHUNK_CANDIDATES overrides, for tests).
+uint64_t Engine::chunk_capacity(uint64_t C, size_t key_bytes) {
+    if (const char *e = std::getenv("CG_CHUNK_CANDIDATES")) {
+        const uint64_t v = std::strtoull(e, nullptr, 10);
+        if (v > 0) return std::min<uint64_t>(v, C);
+    }
+    const double avail = (double)device_bytes_available() + (double)cand0_.bytes + (double)cand1_.bytes;
+    const uint64_t fit = (uint64_t)(avail * 0.85 / (double)(2 * key_bytes + sizeof(uint64_t)));
+    return std::max<uint64_t>(1, std::min<uint64_t>(fit, C));
+}
+
+// One layer in key-range chunks (see chunk.hip). Survivors of each chunk
+// are compacted into a buffer of their own, then concatenated in key order
+// into dst (keep-all: the arena slot of the new layer, capacity out_cap) or
+// into lay_[in] at its exact size. Returns the new layer's size.
+uint64_t Engine::run_chunked(bool ranked, int n, const uint64_t *Ld, uint64_t F, const uint64_t *Lp, uint64_t np,
+                             int k, uint64_t cap, int rank_bits, int bit_lo, int bit_hi, uint64_t *dst,
+                             uint64_t out_cap, uint64_t room, int in) {
+    const int pshift = ranked ? std::max(0, rank_bits - 12) : std::max(bit_lo, bit_hi - 12);
+    const size_t kb = ranked ? sizeof(uint32_t) : sizeof(uint64_t);
+    chunk_hist_.stream = stream_;
+    chunk_hist_.ensure(kChunkBins * sizeof(uint64_t));
+    launch_clear(nullptr, 0, chunk_hist_.as<uint64_t>(), kChunkBins, stream_);
+    launch_prefix_hist(n, ranked, Ld, F, gsel_.as<GenSel>(), k, pshift, chunk_hist_.as<unsigned long long>(), w_);
+    std::vector<uint64_t> h(kChunkBins);
+    CG_HIP(hipMemcpyAsync(h.data(), chunk_hist_.p, sizeof(uint64_t) * kChunkBins, hipMemcpyDeviceToHost, stream_));
+    CG_HIP(hipStreamSynchronize(stream_));
+    // consecutive ranges grouped while they fit
+    struct Chunk {
+        uint32_t lo, hi;
+        uint64_t count;
+    };
+    std::vector<Chunk> chunks;
+    uint64_t cap_used = 0;
+    for (uint32_t b = 0; b < kChunkBins; ++b) {
+        if (h[b] > cap) throw Error(CG_E_NOMEM, "one key range holds more candidates than fit in device memory");
+        if (chunks.empty() || chunks.back().count + h[b] > cap) chunks.push_back({b, b, 0});
+        chunks.back().hi = b + 1;
+        chunks.back().count += h[b];
+        cap_used = std::max(cap_used, chunks.back().count);
+    }
+    cand0_.ensure(std::max<uint64_t>(cap_used, 1) * kb);
+    cand1_.ensure(std::max<uint64_t>(cap_used, 1) * kb);
+    std::vector<std::unique_ptr<DevBuf>> parts;
+    std::vector<uint64_t> part_n;
+    uint64_t total = 0;
+    unsigned long long *cursor = (unsigned long long *)(w_.counter() + 1);
+    for (const Chunk &c : chunks) {
+        if (!c.count) continue;
+        launch_clear(nullptr, 0, w_.counter() + 1, 1, stream_);
+        launch_expand_filter(n, ranked, Ld, F, gsel_.as<GenSel>(), k, pshift, c.lo, c.hi, cand0_.p, c.count, cursor,
+                             w_);
+        uint64_t nj = 0;
+        auto part = std::make_unique<DevBuf>();
+        part->stream = stream_;
+        if (ranked) {
+            uint32_t *c0 = cand0_.as<uint32_t>(), *c1 = cand1_.as<uint32_t>();
+            uint32_t *sorted = radix_sort32(c0, c1, c.count, 0, rank_bits, w_);
+            uint32_t *scratch = sorted == c0 ? c1 : c0;
+            launch_dedup_count_ranked(n, sorted, c.count, Ld, F, Lp, np, scratch, w_.counter(), w_);
+            nj = read_counter();
+            if (nj > c.count) throw Error(CG_E_DEVICE, "chunk size out of range (device error)");
+            if (nj) {
+                part->ensure(nj * sizeof(uint64_t));
+                launch_dedup_gather_ranked(n, scratch, part->as<uint64_t>(), nj, w_);
+            }
+        } else {
+            uint64_t *c0 = cand0_.as<uint64_t>(), *c1 = cand1_.as<uint64_t>();
+            uint64_t *sorted = radix_sort(c0, c1, c.count, bit_lo, bit_hi, w_);
+            uint64_t *scratch = sorted == c0 ? c1 : c0;
+            launch_dedup_count(sorted, c.count, Ld, F, Lp, np, scratch, w_.counter(), w_);
+            nj = read_counter();
+            if (nj > c.count) throw Error(CG_E_DEVICE, "chunk size out of range (device error)");
+            if (nj) {
+                part->ensure(nj * sizeof(uint64_t));
+                launch_dedup_gather(scratch, part->as<uint64_t>(), nj, w_);
+            }
+        }
+        if (nj) {
+            parts.push_back(std::move(part));
+            part_n.push_back(nj);
+            total += nj;
+        }
+    }
+    if (total > room) throw Error(CG_E_DEVICE, "layer size out of range (device error)");
+    if (!dst) {
+        lay_[in].ensure(std::max<uint64_t>(total, 1) * sizeof(uint64_t), 1.25);
+        dst = lay_[in].as<uint64_t>();
+    } else if (total > out_cap) {
+        throw Error(CG_E_DEVICE, "layer larger than its slot (device error)");
+    }
+    uint64_t off = 0;
+    for (size_t i = 0; i < parts.size(); ++i) {
+        CG_HIP(hipMemcpyAsync(dst + off, parts[i]->p, part_n[i] * sizeof(uint64_t), hipMemcpyDeviceToDevice,
+                              stream_));
+        off += part_n[i];
+    }
+    CG_HIP(hipStreamSynchronize(stream_));
+    for (auto &p : parts) p->release();
+    return total;
 }
 
 void Engine::run(const JobSpec &spec, cg_result_t *res) {
@@ -277,8 +384,12 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
         const uint64_t room = spec.orbit_bound > total ? spec.orbit_bound - total : 0;
         const uint64_t out_cap = std::max<uint64_t>(1, std::min(C, room));
         const size_t key_bytes = ranked ? sizeof(uint32_t) : sizeof(uint64_t);
-        cand0_.ensure(C * key_bytes, 1.25);
-        cand1_.ensure(C * key_bytes, 1.25);
+        const uint64_t cap = chunk_capacity(C, key_bytes);
+        const bool chunked = cap < C;
+        if (!chunked) {
+            cand0_.ensure(C * key_bytes, 1.25);
+            cand1_.ensure(C * key_bytes, 1.25);
+        }
 
         const uint64_t *Ld, *Lp;
         uint64_t *out;
@@ -307,7 +418,11 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
         }
 
         uint64_t N = 0;
-        if (ranked) {
+        if (chunked) {
+            uint64_t *dst = keep_all ? out : nullptr;
+            N = run_chunked(ranked, n, Ld, F, Lp, np, k, cap, rank_bits, bit_lo, bit_hi, dst, out_cap, room, in);
+            if (!keep_all) out = lay_[in].as<uint64_t>();
+        } else if (ranked) {
             // candidates as 32-bit lexicographic ranks: half the bytes per
             // sort pass and only ceil(log2 n!) bits to sort
             uint32_t *c0 = cand0_.as<uint32_t>(), *c1 = cand1_.as<uint32_t>();

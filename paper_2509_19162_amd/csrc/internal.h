@@ -206,6 +206,21 @@ void launch_expand_ranked(int n, const uint64_t *frontier, uint64_t F, const Gen
                           int k, uint32_t *out, PipeWork &w);
 // True once the device's arena exists (buffers then grow to exact sizes).
 bool arena_active();
+// Largest block a DevBuf could get now: the arena's largest free range, or
+// the driver's free memory when no arena exists.
+size_t device_bytes_available();
+
+// ---- key-range chunks (chunk.hip) ----
+constexpr uint32_t kChunkBins = 4096;  // ranges by the top 12 bits of the sort key
+// d_hist[b] += candidates whose sort value v has ((v >> pshift) & 4095) == b.
+// ranked: v = 32-bit rank (n <= 12); else v = packed key.
+void launch_prefix_hist(int n, bool ranked, const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,
+                        int pshift, unsigned long long *d_hist, PipeWork &w);
+// Appends the sort values of the candidates with range index in [blo, bhi)
+// to out (uint32 when ranked, else uint64) through *cursor (at most cap).
+void launch_expand_filter(int n, bool ranked, const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,
+                          int pshift, uint32_t blo, uint32_t bhi, void *out, uint64_t cap,
+                          unsigned long long *cursor, PipeWork &w);
 uint64_t dedup_status_words(uint64_t C);
 
 }  // namespace cg

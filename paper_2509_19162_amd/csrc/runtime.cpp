@@ -162,6 +162,24 @@ bool arena_active() {
     return it != arenas().arena.end() && it->second.base;
 }
 
+size_t device_bytes_available() {
+    const int dev = current_device();
+    {
+        std::lock_guard<std::mutex> lk(arenas().mu);
+        auto it = arenas().arena.find(dev);
+        if (it != arenas().arena.end() && it->second.base) {
+            const auto &by_len = it->second.by_len;
+            return by_len.empty() ? 0 : by_len.rbegin()->first;
+        }
+    }
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return free_b;
+}
+
 bool DevBuf::ensure(size_t need, double slack) {
     if (need <= bytes && p) return false;
     const size_t old = bytes;
