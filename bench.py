@@ -141,12 +141,14 @@ def bench_batch(args):
     for _ in range(args.warmup):
         api.growth_batch(jobs, max_layers=512)
     torch.cuda.synchronize()
+    print("[batch] warm-up done", file=sys.stderr, flush=True)
     times, res = [], None
     for _ in range(args.steps):
         t = time.perf_counter()
         res = api.growth_batch(jobs, max_layers=512)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t)
+    print(f"[batch] {args.steps} timed batches done", file=sys.stderr, flush=True)
     elapsed = sum(times)
     states = sum(r.states_expanded for r in res)
     cands = sum(r.candidates for r in res)
@@ -205,18 +207,26 @@ def bench_serving(args):
 
     R = args.requests
     reqs = [I.serving_request(i, n_lo=6, n_hi=args.serving_nmax) for i in range(R)]
+    def progress(msg):
+        print(f"[serving] {msg}", file=sys.stderr, flush=True)
+
     # warm up both paths on the whole trace (device buffers end up cached)
     q = api.GrowthQueue(max_active=256)
     for t in [q.submit(n, g, max_layers=512) for n, fam, g in reqs]:
         q.wait(t)
+    progress("queue warm-up done")
     eng = api.Engine()
-    for n, fam, g in reqs:
+    for i, (n, fam, g) in enumerate(reqs):
         eng.run(n, g, max_layers=512)
+        if i % 25 == 24:
+            progress(f"plain warm-up {i + 1}/{R}")
     # one-at-a-time plain path on the same requests
     t0 = time.perf_counter()
     plain_states = 0
-    for n, fam, g in reqs:
+    for i, (n, fam, g) in enumerate(reqs):
         plain_states += eng.run(n, g, max_layers=512).states_expanded
+        if i % 25 == 24:
+            progress(f"plain pass {i + 1}/{R}")
     plain_dt = time.perf_counter() - t0
     # capacity: every request submitted at once
     t0 = time.perf_counter()
@@ -225,6 +235,7 @@ def bench_serving(args):
         q.wait(t)
     cap_dt = time.perf_counter() - t0
     mu = R / cap_dt
+    progress(f"capacity {mu:.1f} req/s")
     points = {}
     rng = np.random.default_rng(I.SEED)
     for ratio in args.ratios:
@@ -254,6 +265,8 @@ def bench_serving(args):
                               "p99_ms": round(float(np.percentile(lat, 99)), 2),
                               "admit_wait_p50_ms": round(float(np.percentile(wait, 50)), 2),
                               "states_per_s": round(states / dt, 1)}
+        progress(f"rate {ratio} x capacity: p50 {points[str(ratio)]['p50_ms']} ms, "
+                 f"p99 {points[str(ratio)]['p99_ms']} ms")
     q.close()
     torch.cuda.synchronize()
     ref = points.get("0.9") or list(points.values())[-1]

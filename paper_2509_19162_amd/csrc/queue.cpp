@@ -8,7 +8,8 @@
 // Large jobs (n > 13, an orbit above 2^21 states, or an estimate above a
 // quarter of the budget) run on separate lanes, each a thread with its own
 // engine and stream, so their work overlaps with the shared group's on the
-// device and they do not hold back the small jobs' super-steps.
+// device and they do not hold back the small jobs' super-steps; from n = 12
+// such permutation jobs use the bitmask engine.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -21,6 +22,7 @@
 #include <thread>
 
 #include "batch.h"
+#include "bitmap.h"
 
 namespace cg {
 
@@ -239,6 +241,15 @@ int cg_queue_submit(cg_queue_t *q, const cg_job_t *job, cg_result_t *res_slot, u
     if ((int)(q->queued.size() + q->big_queued.size()) >= max_q) return CG_E_BUSY;
     r->ticket = q->next_ticket++;
     r->big = r->spec.n > cg::kSharedN || r->spec.orbit_bound > cg::kLargeOrbit || r->bytes > q->budget / 4;
+    // large permutation jobs from n = 12 run in the bitmask engine: 3 bits
+    // per state of S_n instead of 8-byte layers and candidate arrays (an
+    // S_13 job holds 2.3 GB there); results are the same
+    if (r->big && r->spec.n >= 12 && !(r->spec.flags & CG_PACKED_SORT) && cg::bitmask_unsupported(r->spec).empty()) {
+        r->spec.flags |= CG_BITMASK;
+        uint64_t states = 1;
+        for (int i = 2; i <= r->spec.n; ++i) states *= (uint64_t)i;
+        r->bytes = 3 * ((states + 31) / 32) * 4 + (64u << 20);
+    }
     *ticket = r->ticket;
     cg::QueueReq *p = r.get();
     q->reqs[r->ticket] = std::move(r);

@@ -74,3 +74,31 @@ def test_queue_rejects_invalid_job():
     with api.GrowthQueue() as q:
         with pytest.raises(api.CGError):
             q.submit(4, [[0, 1, 1, 2]])
+
+
+def mahonian(n):
+    poly = [1]
+    for i in range(1, n + 1):
+        nxt = [0] * (len(poly) + i - 1)
+        for a, c in enumerate(poly):
+            for b in range(i):
+                nxt[a + b] += c
+        poly = nxt
+    return poly
+
+
+def test_queue_serves_s13_requests_beside_small_ones(oracle_c):
+    # n = 12, 13 permutation requests take the bitmask engine on a large
+    # lane; small requests keep flowing through the shared group meanwhile
+    with api.GrowthQueue(max_active=32) as q:
+        t13 = q.submit(13, I.coxeter(13), max_layers=128)
+        t12 = q.submit(12, I.pancake(12), max_layers=64)
+        small = [I.serving_request(i, n_lo=5, n_hi=8) for i in range(40)]
+        ts = [q.submit(n, g, max_layers=512) for n, _, g in small]
+        for (n, fam, g), t in zip(small, ts):
+            r = q.wait(t, timeout_s=120)
+            assert r.sizes == oracle_c.growth(n, g, max_layers=512)[0]
+        r12 = q.wait(t12, timeout_s=120)
+        assert sum(r12.sizes) == 479001600 and len(r12.sizes) == 15
+        r13 = q.wait(t13, timeout_s=300)
+        assert r13.sizes == mahonian(13)
