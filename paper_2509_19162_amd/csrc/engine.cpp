@@ -12,6 +12,7 @@
 // The loop stops at an empty layer (complete), after max_layers layers, or
 // after recording the first layer larger than max_frontier (truncated).
 #include "engine.h"
+#include "batch.h"
 #include "bitmap.h"
 
 #include "perm_rank.h"
@@ -112,7 +113,9 @@ Engine::Engine(hipStream_t user_stream) {
         own_stream_ = true;
     }
     w_.init(stream_);
-    for (DevBuf *b : {&gsel_, &cand0_, &cand1_, &lay_[0], &lay_[1], &lay_[2], &arena_, &stage_}) b->stream = stream_;
+    for (DevBuf *b : {&gsel_, &cand0_, &cand1_, &lay_[0], &lay_[1], &lay_[2], &arena_, &stage_, &chunk_hist_, &vis_[0],
+                      &vis_[1]})
+        b->stream = stream_;
     prof_.stream = stream_;
     CG_HIP(hipHostMalloc((void **)&host_small_, 64, hipHostMallocDefault));
 }
@@ -121,7 +124,8 @@ Engine::~Engine() {
     delete wg_;
     if (host_small_) (void)hipHostFree(host_small_);
     // buffers go back to the device cache while their stream still exists
-    for (DevBuf *b : {&gsel_, &cand0_, &cand1_, &lay_[0], &lay_[1], &lay_[2], &arena_, &stage_, &chunk_hist_})
+    for (DevBuf *b : {&gsel_, &cand0_, &cand1_, &lay_[0], &lay_[1], &lay_[2], &arena_, &stage_, &chunk_hist_,
+                      &vis_[0], &vis_[1]})
         b->release();
     for (DevBuf *b : {&w_.hist, &w_.base, &w_.small, &w_.status, &w_.bounds, &w_.tile_cnt, &w_.tile_off,
                       &w_.kill})
@@ -188,9 +192,9 @@ uint64_t Engine::chunk_capacity(uint64_t C, size_t key_bytes) {
 // are compacted into a buffer of their own, then concatenated in key order
 // into dst (keep-all: the arena slot of the new layer, capacity out_cap) or
 // into lay_[in] at its exact size. Returns the new layer's size.
-uint64_t Engine::run_chunked(bool ranked, int n, const uint64_t *Ld, uint64_t F, const uint64_t *Lp, uint64_t np,
-                             int k, uint64_t cap, int rank_bits, int bit_lo, int bit_hi, uint64_t *dst,
-                             uint64_t out_cap, uint64_t room, int in) {
+uint64_t Engine::run_chunked(bool ranked, int n, const uint64_t *Ld, uint64_t F, const uint64_t *Ra, uint64_t na,
+                             const uint64_t *Rb, uint64_t nb, int k, uint64_t cap, int rank_bits, int bit_lo,
+                             int bit_hi, uint64_t *dst, uint64_t out_cap, uint64_t room, int in) {
     const int pshift = ranked ? std::max(0, rank_bits - 12) : std::max(bit_lo, bit_hi - 12);
     const size_t kb = ranked ? sizeof(uint32_t) : sizeof(uint64_t);
     chunk_hist_.stream = stream_;
@@ -232,7 +236,7 @@ uint64_t Engine::run_chunked(bool ranked, int n, const uint64_t *Ld, uint64_t F,
             uint32_t *c0 = cand0_.as<uint32_t>(), *c1 = cand1_.as<uint32_t>();
             uint32_t *sorted = radix_sort32(c0, c1, c.count, 0, rank_bits, w_);
             uint32_t *scratch = sorted == c0 ? c1 : c0;
-            launch_dedup_count_ranked(n, sorted, c.count, Ld, F, Lp, np, scratch, w_.counter(), w_);
+            launch_dedup_count_ranked(n, sorted, c.count, Ra, na, Rb, nb, scratch, w_.counter(), w_);
             nj = read_counter();
             if (nj > c.count) throw Error(CG_E_DEVICE, "chunk size out of range (device error)");
             if (nj) {
@@ -243,7 +247,7 @@ uint64_t Engine::run_chunked(bool ranked, int n, const uint64_t *Ld, uint64_t F,
             uint64_t *c0 = cand0_.as<uint64_t>(), *c1 = cand1_.as<uint64_t>();
             uint64_t *sorted = radix_sort(c0, c1, c.count, bit_lo, bit_hi, w_);
             uint64_t *scratch = sorted == c0 ? c1 : c0;
-            launch_dedup_count(sorted, c.count, Ld, F, Lp, np, scratch, w_.counter(), w_);
+            launch_dedup_count(sorted, c.count, Ra, na, Rb, nb, scratch, w_.counter(), w_);
             nj = read_counter();
             if (nj > c.count) throw Error(CG_E_DEVICE, "chunk size out of range (device error)");
             if (nj) {
@@ -311,8 +315,10 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
     }
     const int n = spec.n, k = spec.k;
     const bool keep_all = (spec.flags & CG_KEEP_ALL_LAYERS) != 0;
+    // A set not closed under inverses can reach any earlier layer, so the
+    // new layer is taken against every state seen so far: a sorted visited
+    // array into which each new layer is merged.
     const bool directed = !spec.inverse_closed;
-    if (directed) throw Error(CG_E_UNSUPPORTED, "directed growth is not available in this build");
 
     hipEvent_t ev0, ev1;
     CG_HIP(hipEventCreate(&ev0));
@@ -349,6 +355,13 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
     }
     int ip = 0, ic = 1, in = 2;  // indices of L_{d-1}, L_d, L_{d+1} in lay_
     uint64_t np = 0, F = 1;
+    int iv = 0;          // directed: vis_[iv] holds every visited state, sorted
+    uint64_t nvis = 0;
+    if (directed) {
+        vis_[0].ensure(64);
+        CG_HIP(hipMemcpyAsync(vis_[0].p, &key0, 8, hipMemcpyHostToDevice, stream_));
+        nvis = 1;
+    }
     export_layer(spec, keep_all ? arena_.as<uint64_t>() : lay_[1].as<uint64_t>(), 1, written);
 
     const int bit_lo = 4, bit_hi = 4 * n;
@@ -417,10 +430,17 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             out = nullptr;  // sized once N is known
         }
 
+        // the states a candidate must not be: layers d and d-1, or (directed)
+        // every visited state
+        const uint64_t *Ra = directed ? vis_[iv].as<uint64_t>() : Ld;
+        const uint64_t na = directed ? nvis : F;
+        const uint64_t *Rb = directed ? nullptr : Lp;
+        const uint64_t nb = directed ? 0 : np;
         uint64_t N = 0;
         if (chunked) {
             uint64_t *dst = keep_all ? out : nullptr;
-            N = run_chunked(ranked, n, Ld, F, Lp, np, k, cap, rank_bits, bit_lo, bit_hi, dst, out_cap, room, in);
+            N = run_chunked(ranked, n, Ld, F, Ra, na, Rb, nb, k, cap, rank_bits, bit_lo, bit_hi, dst, out_cap, room,
+                            in);
             if (!keep_all) out = lay_[in].as<uint64_t>();
         } else if (ranked) {
             // candidates as 32-bit lexicographic ranks: half the bytes per
@@ -428,7 +448,7 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             uint32_t *c0 = cand0_.as<uint32_t>(), *c1 = cand1_.as<uint32_t>();
             const uint32_t *sorted = expand_rank_sort(n, Ld, F, gsel_.as<GenSel>(), k, c0, c1, rank_bits, w_);
             uint32_t *scratch = sorted == c0 ? c1 : c0;
-            launch_dedup_count_ranked(n, sorted, C, Ld, F, Lp, np, scratch, w_.counter(), w_);
+            launch_dedup_count_ranked(n, sorted, C, Ra, na, Rb, nb, scratch, w_.counter(), w_);
             N = read_counter();
             if (N > C || N > room) throw Error(CG_E_DEVICE, "layer size out of range (device error)");
             if (!keep_all) {
@@ -440,7 +460,7 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             const uint64_t *sorted = expand_sort(Ld, F, gsel_.as<GenSel>(), k, cand0_.as<uint64_t>(),
                                                  cand1_.as<uint64_t>(), bit_lo, bit_hi, w_);
             uint64_t *scratch = sorted == cand0_.as<uint64_t>() ? cand1_.as<uint64_t>() : cand0_.as<uint64_t>();
-            launch_dedup_count(sorted, C, Ld, F, Lp, np, scratch, w_.counter(), w_);
+            launch_dedup_count(sorted, C, Ra, na, Rb, nb, scratch, w_.counter(), w_);
             N = read_counter();
             if (N > C || N > room) throw Error(CG_E_DEVICE, "layer size out of range (device error)");
             if (!keep_all) {
@@ -462,6 +482,13 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
         sizes[layers++] = N;
         export_layer(spec, out, N, written);
         total += N;
+        if (directed) {
+            // visited := visited merged with the new layer (disjoint, both sorted)
+            vis_[iv ^ 1].ensure((nvis + N) * sizeof(uint64_t), 1.25);
+            launch_merge(vis_[iv].as<uint64_t>(), nvis, out, N, vis_[iv ^ 1].as<uint64_t>(), stream_);
+            iv ^= 1;
+            nvis += N;
+        }
         if (keep_all) {
             off.push_back(total);
         } else {

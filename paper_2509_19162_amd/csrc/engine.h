@@ -51,15 +51,15 @@ private:
     void export_layer(const JobSpec &spec, const uint64_t *d_keys, uint64_t count,
                       uint64_t &written);
     uint64_t chunk_capacity(uint64_t C, size_t key_bytes);
-    uint64_t run_chunked(bool ranked, int n, const uint64_t *Ld, uint64_t F, const uint64_t *Lp, uint64_t np, int k,
-                         uint64_t cap, int rank_bits, int bit_lo, int bit_hi, uint64_t *dst, uint64_t out_cap,
-                         uint64_t room, int in);
+    uint64_t run_chunked(bool ranked, int n, const uint64_t *Ld, uint64_t F, const uint64_t *Ra, uint64_t na,
+                         const uint64_t *Rb, uint64_t nb, int k, uint64_t cap, int rank_bits, int bit_lo, int bit_hi,
+                         uint64_t *dst, uint64_t out_cap, uint64_t room, int in);
 
     hipStream_t stream_ = nullptr;
     bool own_stream_ = false;
     PipeWork w_;
     Profiler prof_;
-    DevBuf gsel_, cand0_, cand1_, lay_[3], arena_, stage_, chunk_hist_;
+    DevBuf gsel_, cand0_, cand1_, lay_[3], arena_, stage_, chunk_hist_, vis_[2];
     class WgRunner *wg_ = nullptr;  // small-job engine (created on first use)
     uint64_t *host_small_ = nullptr;  // pinned: counter + error flag
 };
