@@ -272,6 +272,36 @@ void cg_queue_destroy(cg_queue_t *q);
  */
 void cg_release_cached_memory(void);
 
+/* ---- growth statistics (host) -------------------------------------------- */
+/*
+ * The growth read as a distribution of the distance d from the start over
+ * the reached states, p(d) = sizes[d] / total (paper, section "Table of
+ * results: hundreds of new conjectures on Cayley graphs": mean, mode,
+ * variance, skewness, kurtosis, and a Gaussian or Gumbel shape fitted to
+ * the growth). Moments are population moments; kurtosis is the excess
+ * kurtosis (m4 / var^2 - 3). The fits match moments: Gaussian (mean, sd);
+ * Gumbel for the maximum when skewness >= 0, for the minimum otherwise,
+ * with scale sd * sqrt(6) / pi and location mean -/+ 0.5772... * scale.
+ * Each fit's distance is the total variation between p and the model's
+ * mass on [d - 1/2, d + 1/2).
+ */
+typedef struct cg_growth_stats {
+    uint64_t total;      /* states reached: sum of sizes                     */
+    int diameter;        /* index of the last non-empty layer                */
+    int mode;            /* first index of the largest layer                 */
+    uint64_t max_layer;  /* size of that layer                               */
+    uint64_t antipodes;  /* size of the last layer                           */
+    double mean, variance, skewness, kurtosis;
+    double gauss_mu, gauss_sigma, gauss_tv;
+    double gumbel_mu, gumbel_beta, gumbel_tv;
+    int gumbel_min;      /* 1: Gumbel of the minimum (left-skewed)          */
+    int best_fit;        /* 0 Gaussian, 1 Gumbel (smaller distance)          */
+} cg_growth_stats_t;
+
+/* sizes: num_layers >= 1 layer sizes, host memory; trailing zeros ignored.
+   Returns CG_OK, or CG_E_INVAL (NULL pointer, no layers, all zero). */
+int cg_growth_stats(const uint64_t *sizes, int num_layers, cg_growth_stats_t *out);
+
 /* ---- errors -------------------------------------------------------------- */
 const char *cg_strerror(int code);
 /* Detail string of the last failure on the calling thread ("" if none). */

@@ -96,6 +96,28 @@ class CgQueueOpts(ctypes.Structure):
     ]
 
 
+class CgGrowthStats(ctypes.Structure):
+    _fields_ = [
+        ("total", ctypes.c_uint64),
+        ("diameter", ctypes.c_int),
+        ("mode", ctypes.c_int),
+        ("max_layer", ctypes.c_uint64),
+        ("antipodes", ctypes.c_uint64),
+        ("mean", ctypes.c_double),
+        ("variance", ctypes.c_double),
+        ("skewness", ctypes.c_double),
+        ("kurtosis", ctypes.c_double),
+        ("gauss_mu", ctypes.c_double),
+        ("gauss_sigma", ctypes.c_double),
+        ("gauss_tv", ctypes.c_double),
+        ("gumbel_mu", ctypes.c_double),
+        ("gumbel_beta", ctypes.c_double),
+        ("gumbel_tv", ctypes.c_double),
+        ("gumbel_min", ctypes.c_int),
+        ("best_fit", ctypes.c_int),
+    ]
+
+
 # (name, restype, argtypes) of every exported entry point
 SIGNATURES = [
     ("cg_growth", ctypes.c_int, [ctypes.c_int, u8p, ctypes.c_int, ctypes.c_int, u64p]),
@@ -113,6 +135,7 @@ SIGNATURES = [
     ("cg_queue_cancel", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     ("cg_queue_destroy", None, [ctypes.c_void_p]),
     ("cg_release_cached_memory", None, []),
+    ("cg_growth_stats", ctypes.c_int, [u64p, ctypes.c_int, ctypes.POINTER(CgGrowthStats)]),
     ("cg_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("cg_last_error", ctypes.c_char_p, []),
     ("cg_test_pack", ctypes.c_int, [ctypes.c_int, u8p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),

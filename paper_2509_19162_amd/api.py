@@ -226,6 +226,21 @@ def growth_batch(jobs, max_layers: int = 256, max_active: int = 0, budget_bytes:
     return out
 
 
+def growth_stats(sizes: Sequence[int]) -> Dict[str, float]:
+    """Statistics of a growth vector (``cg_growth_stats``): mean, mode,
+    variance, skewness, excess kurtosis, moment-matched Gaussian and Gumbel
+    fits and their total-variation distances."""
+    a = np.ascontiguousarray(np.asarray(list(sizes), dtype=np.uint64))
+    if a.size == 0:
+        raise CGError(N.CG_E_INVAL, "empty growth vector")
+    st = N.CgGrowthStats()
+    _check(N.lib().cg_growth_stats(a.ctypes.data_as(N.u64p), int(a.size), ctypes.byref(st)))
+    out = {name: getattr(st, name) for name, _ in N.CgGrowthStats._fields_}
+    out["gumbel_min"] = bool(out["gumbel_min"])
+    out["best_fit"] = "gumbel" if out["best_fit"] else "gaussian"
+    return out
+
+
 _LIVE_QUEUES: "weakref.WeakSet[GrowthQueue]" = weakref.WeakSet()
 
 

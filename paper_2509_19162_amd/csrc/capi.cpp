@@ -94,6 +94,14 @@ int cg_growth(int n, const uint8_t *gens, int n_gens, int max_layers, uint64_t *
     return cg_growth_ex(&job, &res, nullptr);
 }
 
+int cg_growth_stats(const uint64_t *sizes, int num_layers, cg_growth_stats_t *out) {
+    return guarded([&]() -> int {
+        if (!sizes || !out || num_layers < 1) throw cg::Error(CG_E_INVAL, "NULL sizes or result, or no layers");
+        cg::growth_stats(sizes, num_layers, out);
+        return CG_OK;
+    });
+}
+
 int cg_growth_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_batch_opts_t *opts) {
     return guarded([&]() -> int {
         if (n_jobs < 0 || (n_jobs > 0 && (!jobs || !results)))

@@ -10,6 +10,8 @@
 #include <utility>
 #include <vector>
 
+#include "../../include/cayleygrowth.h"
+
 namespace cg {
 
 // ---------------------------------------------------------------------------
@@ -115,6 +117,8 @@ struct DevBuf {
 // Returns the device arena to the driver when no buffer uses it
 // (cg_release_cached_memory).
 void release_cached_device_memory();
+// Statistics of a growth vector (stats.cpp); throws Error(CG_E_INVAL).
+void growth_stats(const uint64_t *sizes, int num_layers, cg_growth_stats_t *out);
 
 struct PipeWork {
     DevBuf hist;     // uint64 [kMaxPasses][256]: digit counts of every pass
