@@ -175,16 +175,21 @@ void fill_kstats(const Profiler &p, cg_result_t *res) {
     }
 }
 
-// Candidates one layer may hold at once: all of them when two candidate
-// arrays plus the new layer fit in the free device memory, else a chunk of
-// that size (CG_CHUNK_CANDIDATES overrides, for tests).
-uint64_t Engine::chunk_capacity(uint64_t C, size_t key_bytes) {
+// CG_CHUNK_CANDIDATES (tests) forces chunks of at most that many candidates.
+uint64_t Engine::forced_chunk(uint64_t C) {
     if (const char *e = std::getenv("CG_CHUNK_CANDIDATES")) {
         const uint64_t v = std::strtoull(e, nullptr, 10);
         if (v > 0) return std::min<uint64_t>(v, C);
     }
-    const double avail = (double)device_bytes_available() + (double)cand0_.bytes + (double)cand1_.bytes;
-    const uint64_t fit = (uint64_t)(avail * 0.85 / (double)(2 * key_bytes + sizeof(uint64_t)));
+    return C;
+}
+
+// Candidates per chunk when a layer's candidate arrays do not fit: two
+// arrays of that many keys in 60% of the largest free block, the rest left
+// for the chunks' survivors.
+uint64_t Engine::chunk_capacity(uint64_t C, size_t key_bytes) {
+    const double avail = (double)device_bytes_available();
+    const uint64_t fit = (uint64_t)(avail * 0.6 / (double)(2 * key_bytes));
     return std::max<uint64_t>(1, std::min<uint64_t>(fit, C));
 }
 
@@ -397,12 +402,21 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
         const uint64_t room = spec.orbit_bound > total ? spec.orbit_bound - total : 0;
         const uint64_t out_cap = std::max<uint64_t>(1, std::min(C, room));
         const size_t key_bytes = ranked ? sizeof(uint32_t) : sizeof(uint64_t);
-        const uint64_t cap = chunk_capacity(C, key_bytes);
-        const bool chunked = cap < C;
-        if (!chunked) {
-            cand0_.ensure(C * key_bytes, 1.25);
-            cand1_.ensure(C * key_bytes, 1.25);
+        // all candidates at once when both arrays fit; otherwise key-range
+        // chunks sized to the memory left
+        uint64_t cap = forced_chunk(C);
+        if (cap >= C) {
+            try {
+                cand0_.ensure(C * key_bytes, 1.25);
+                cand1_.ensure(C * key_bytes, 1.25);
+            } catch (const Error &e) {
+                if (e.code != CG_E_NOMEM) throw;
+                cand0_.release();
+                cand1_.release();
+                cap = chunk_capacity(C, key_bytes);
+            }
         }
+        const bool chunked = cap < C;
 
         const uint64_t *Ld, *Lp;
         uint64_t *out;

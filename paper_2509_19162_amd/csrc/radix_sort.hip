@@ -293,6 +293,10 @@ __global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
     const auto T = src.tile(tile);
     const uint32_t nvalid = T.n;
 
+    // A short (last) tile is padded with all-ones keys, which rank as the
+    // largest digit after every real key (index order); their count is
+    // taken off that digit's published count, so no step below needs a
+    // bounds check, and only the final write stops at nvalid.
     // Wave w owns keys [w*S, (w+1)*S) of the tile (S = kWaveSeg); item j of
     // lane l is key w*S + j*64 + l, so (wave, item, lane) order is index order and
     // the per-wave running counts give a stable rank.
@@ -316,16 +320,10 @@ __global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
 #pragma unroll
     for (int j0 = 0; j0 < kIpt; j0 += kRows) {
         uint32_t d[kRows];
-        bool valid[kRows];
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) {
-            const uint32_t i = wave * kWaveSeg + (j0 + r) * kWave + lane;
-            valid[r] = i < nvalid;
-            d[r] = (uint32_t)(key[j0 + r] >> shift) & dmask;
-        }
+        for (int r = 0; r < kRows; ++r) d[r] = (uint32_t)(key[j0 + r] >> shift) & dmask;
 #pragma unroll
-        for (int r = 0; r < kRows; ++r)
-            if (valid[r]) atomicOr(&s_match[r][wave][d[r]], 1ull << lane);
+        for (int r = 0; r < kRows; ++r) atomicOr(&s_match[r][wave][d[r]], 1ull << lane);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         uint64_t m[kRows][kRows];
@@ -333,14 +331,13 @@ __global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
 #pragma unroll
-            for (int q = 0; q < kRows; ++q) m[r][q] = valid[r] ? s_match[q][wave][d[r]] : 0ull;
-            old[r] = valid[r] ? s_cnt[wave][d[r]] : 0u;
+            for (int q = 0; q < kRows; ++q) m[r][q] = s_match[q][wave][d[r]];
+            old[r] = s_cnt[wave][d[r]];
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int r = 0; r < kRows; ++r)
-            if (valid[r]) s_match[r][wave][d[r]] = 0ull;
+        for (int r = 0; r < kRows; ++r) s_match[r][wave][d[r]] = 0ull;
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
             uint32_t before = mask_rank(m[r][r]);
@@ -356,7 +353,11 @@ __global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
                 }
             }
             rank[j0 + r] = (old[r] + before) | (d[r] << 16);  // rank < 2^16 beside the digit
-            if (valid[r] && first) s_cnt[wave][d[r]] = old[r] + total;
+            // materialise the packed rank here: left to itself the compiler
+            // keeps digit, count and lane rank of every row apart until the
+            // scatter, which costs two extra registers per row
+            __asm__ volatile("" : "+v"(rank[j0 + r]));
+            if (first) s_cnt[wave][d[r]] = old[r] + total;
         }
     }
     __syncthreads();
@@ -371,28 +372,31 @@ __global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
             s_cnt[w][d] = run;
             run += c;
         }
+        // the padding keys all hold the largest digit: not published
+        const uint32_t pub = run - (d == dmask ? (uint32_t)kTileK - nvalid : 0u);
         uint64_t *my = status + (uint64_t)tile * kRadix + d;
         uint64_t excl = 0;
         if (tile == 0) {
-            lb_store(my, lb_word(epoch, kFlagInclusive, run));
+            lb_store(my, lb_word(epoch, kFlagInclusive, pub));
         } else {
-            lb_store(my, lb_word(epoch, kFlagAggregate, run));
+            lb_store(my, lb_word(epoch, kFlagAggregate, pub));
             excl = lb_lookback(status + d, kRadix, tile, epoch, err);
-            lb_store(my, lb_word(epoch, kFlagInclusive, excl + run));
+            lb_store(my, lb_word(epoch, kFlagInclusive, excl + pub));
         }
         s_gstart[d] = (uint64_t)digit_base[d] + excl;
         uint32_t tot;
-        s_lstart[d] = block_excl_scan<kWaves>(run, s_scan, &tot);
+        const uint32_t lstart = block_excl_scan<kWaves>(run, s_scan, &tot);
+        s_lstart[d] = lstart;
+        // each wave's slot for this digit in the tile-sorted order
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) s_cnt[w][d] += lstart;
     }
     __syncthreads();
 
 #pragma unroll
     for (int j = 0; j < kIpt; ++j) {
-        const uint32_t i = wave * kWaveSeg + j * kWave + lane;
-        if (i < nvalid) {
-            const uint32_t d = rank[j] >> 16;
-            s_keys[s_lstart[d] + s_cnt[wave][d] + (rank[j] & 0xFFFFu)] = key[j];
-        }
+        const uint32_t d = rank[j] >> 16;
+        s_keys[s_cnt[wave][d] + (rank[j] & 0xFFFFu)] = key[j];
     }
     __syncthreads();
 
