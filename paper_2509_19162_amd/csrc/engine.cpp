@@ -128,7 +128,7 @@ Engine::~Engine() {
                       &vis_[0], &vis_[1]})
         b->release();
     for (DevBuf *b : {&w_.hist, &w_.base, &w_.small, &w_.status, &w_.bounds, &w_.tile_cnt, &w_.tile_off,
-                      &w_.kill})
+                      &w_.kill, &w_.tcnt, &w_.toff, &w_.bsum})
         b->release();
     if (own_stream_) {
         (void)hipStreamSynchronize(stream_);

@@ -129,6 +129,9 @@ struct PipeWork {
     DevBuf tile_cnt; // uint32 [tiles]: survivors per dedup tile
     DevBuf tile_off; // uint64 [tiles]: output offset per dedup tile
     DevBuf kill;     // uint8 [C]: candidates found in a reference layer
+    DevBuf tcnt;     // uint32 [tiles][256]: digit counts per sort tile (reduce-then-scan)
+    DevBuf toff;     // uint64 [tiles][256]: first output position per (tile, digit)
+    DevBuf bsum;     // uint64 [tile runs][256]: digit sums per run of 1024 tiles
     uint32_t epoch = 0;  // 16-bit epoch of the look-back words
     uint32_t dedup_tiles = 0;  // tiles of the last launch_dedup_count
     hipStream_t stream = nullptr;

@@ -21,6 +21,9 @@
 // The first pass of expand_sort() regenerates the candidates from the
 // frontier (permute-expand fused into the pass), so the unsorted candidate
 // array is never written.
+#include <cstdlib>
+#include <type_traits>
+
 #include "internal.h"
 #include "device_util.h"
 #include "expand_device.h"
@@ -259,11 +262,15 @@ __global__ void clear_kernel(unsigned long long *__restrict__ a, uint32_t na,
 #else
 #define CG_SORT_ATTR
 #endif
-template <class Src>
+// Lookback = true: tiles take tickets and chain their digit offsets by
+// decoupled look-back. Lookback = false: tile = block index and each
+// tile's digit offsets come precomputed in tile_off (reduce-then-scan).
+template <class Src, bool Lookback>
 __global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
     Src src, typename Src::Key *__restrict__ out, uint64_t total, int shift, uint32_t dmask,
     const unsigned long long *__restrict__ digit_base, uint64_t *__restrict__ status,
-    uint32_t *__restrict__ ticket, uint32_t epoch, uint32_t *__restrict__ err) {
+    uint32_t *__restrict__ ticket, uint32_t epoch, uint32_t *__restrict__ err,
+    const uint64_t *__restrict__ tile_off) {
     using K = typename Src::Key;
     constexpr int kIpt = TileOf<K>::ipt;
     constexpr int kTileK = TileOf<K>::tile;
@@ -285,11 +292,11 @@ __global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = tid / kWave;
 
-    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    if (Lookback && tid == 0) s_tile = atomicAdd(ticket, 1u);
     for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0;
     for (int i = tid; i < kRows * kWaves * kRadix; i += kBlock) (&s_match[0][0][0])[i] = 0;
     __syncthreads();
-    const uint32_t tile = s_tile;
+    const uint32_t tile = Lookback ? s_tile : blockIdx.x;
     const auto T = src.tile(tile);
     const uint32_t nvalid = T.n;
 
@@ -372,18 +379,22 @@ __global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
             s_cnt[w][d] = run;
             run += c;
         }
-        // the padding keys all hold the largest digit: not published
-        const uint32_t pub = run - (d == dmask ? (uint32_t)kTileK - nvalid : 0u);
-        uint64_t *my = status + (uint64_t)tile * kRadix + d;
-        uint64_t excl = 0;
-        if (tile == 0) {
-            lb_store(my, lb_word(epoch, kFlagInclusive, pub));
+        if constexpr (Lookback) {
+            // the padding keys all hold the largest digit: not published
+            const uint32_t pub = run - (d == dmask ? (uint32_t)kTileK - nvalid : 0u);
+            uint64_t *my = status + (uint64_t)tile * kRadix + d;
+            uint64_t excl = 0;
+            if (tile == 0) {
+                lb_store(my, lb_word(epoch, kFlagInclusive, pub));
+            } else {
+                lb_store(my, lb_word(epoch, kFlagAggregate, pub));
+                excl = lb_lookback(status + d, kRadix, tile, epoch, err);
+                lb_store(my, lb_word(epoch, kFlagInclusive, excl + pub));
+            }
+            s_gstart[d] = (uint64_t)digit_base[d] + excl;
         } else {
-            lb_store(my, lb_word(epoch, kFlagAggregate, pub));
-            excl = lb_lookback(status + d, kRadix, tile, epoch, err);
-            lb_store(my, lb_word(epoch, kFlagInclusive, excl + pub));
+            s_gstart[d] = tile_off[(uint64_t)tile * kRadix + d];
         }
-        s_gstart[d] = (uint64_t)digit_base[d] + excl;
         uint32_t tot;
         const uint32_t lstart = block_excl_scan<kWaves>(run, s_scan, &tot);
         s_lstart[d] = lstart;
@@ -411,6 +422,75 @@ __global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
     }
 }
 
+// ---- 3b. reduce-then-scan: per-tile digit counts and their offsets ------------
+// Same tiles (and the same load pattern) as the scatter pass; only the real
+// keys of a short tile are counted.
+template <class Src>
+__global__ __launch_bounds__(kBlock) void tile_count_kernel(Src src, int shift, uint32_t dmask,
+                                                            uint32_t *__restrict__ tcnt) {
+    using K = typename Src::Key;
+    constexpr int kIpt = TileOf<K>::ipt;
+    constexpr int kWaveSeg = TileOf<K>::wave_seg;
+    __shared__ uint32_t s_h[kRadix];
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    s_h[tid] = 0;
+    __syncthreads();
+    const auto T = src.tile(blockIdx.x);
+    uint32_t cur = 0, run = 0;
+#pragma unroll
+    for (int j = 0; j < kIpt; ++j) {
+        const uint32_t i = wave * kWaveSeg + j * kWave + lane;
+        if (i < T.n) {
+            const uint32_t d = (uint32_t)(T.get(i) >> shift) & dmask;
+            if (d != cur) {
+                if (run) atomicAdd(&s_h[cur], run);
+                cur = d;
+                run = 1;
+            } else {
+                ++run;
+            }
+        }
+    }
+    if (run) atomicAdd(&s_h[cur], run);
+    __syncthreads();
+    tcnt[(uint64_t)blockIdx.x * kRadix + tid] = s_h[tid];
+}
+
+// Sums of each digit's counts over runs of `tb` tiles (one block per run).
+__global__ __launch_bounds__(kBlock) void tile_colsum_kernel(const uint32_t *__restrict__ tcnt, uint32_t ntiles,
+                                                             uint32_t tb, uint64_t *__restrict__ bsum) {
+    const uint32_t b = blockIdx.x, d = threadIdx.x;
+    const uint32_t t_end = min((b + 1) * tb, ntiles);
+    uint64_t acc = 0;
+    for (uint32_t t = b * tb; t < t_end; ++t) acc += tcnt[(uint64_t)t * kRadix + d];
+    bsum[(uint64_t)b * kRadix + d] = acc;
+}
+
+// Exclusive scan of the run sums per digit, starting at the digit's base.
+__global__ __launch_bounds__(kBlock) void bsum_scan_kernel(uint64_t *__restrict__ bsum, uint32_t nb,
+                                                           const unsigned long long *__restrict__ digit_base) {
+    const uint32_t d = threadIdx.x;
+    uint64_t acc = digit_base[d];
+    for (uint32_t b = 0; b < nb; ++b) {
+        const uint64_t v = bsum[(uint64_t)b * kRadix + d];
+        bsum[(uint64_t)b * kRadix + d] = acc;
+        acc += v;
+    }
+}
+
+// First output position of every (tile, digit).
+__global__ __launch_bounds__(kBlock) void tile_offset_kernel(const uint32_t *__restrict__ tcnt, uint32_t ntiles,
+                                                             uint32_t tb, const uint64_t *__restrict__ bsum,
+                                                             uint64_t *__restrict__ toff) {
+    const uint32_t b = blockIdx.x, d = threadIdx.x;
+    const uint32_t t_end = min((b + 1) * tb, ntiles);
+    uint64_t acc = bsum[(uint64_t)b * kRadix + d];
+    for (uint32_t t = b * tb; t < t_end; ++t) {
+        toff[(uint64_t)t * kRadix + d] = acc;
+        acc += tcnt[(uint64_t)t * kRadix + d];
+    }
+}
+
 PassDesc make_passes(int bit_lo, int bit_hi) {
     PassDesc pd{};
     pd.passes = 0;
@@ -429,6 +509,15 @@ uint32_t hist_grid(uint32_t ntiles) {
 }
 
 constexpr uint64_t kSkipCheckMin = 1ull << 22;
+
+// Reduce-then-scan for passes over at least CG_SORT_RTS_MIN keys (default 0
+// = never: on MI355X the look-back pass measured faster, 71 against 113 ms
+// of sort passes for S_12 pancake).
+bool use_reduce_then_scan(uint64_t count) {
+    const char *e = std::getenv("CG_SORT_RTS_MIN");
+    const uint64_t min_keys = e ? std::strtoull(e, nullptr, 10) : 0ull;
+    return min_keys && count >= min_keys;
+}
 
 template <class Src>
 typename Src::Key *run_sort(const Src &first_src, uint64_t count, typename Src::Key *buf0,
@@ -488,25 +577,47 @@ typename Src::Key *run_sort(const Src &first_src, uint64_t count, typename Src::
 
     K *cur_out = buf0;
     const K *cur_in = nullptr;
+    // Either one scatter pass with decoupled look-back, or reduce-then-scan
+    // (a counting pass over the tiles, a scan of the counts, then the
+    // scatter with known offsets).
+    const bool rts = use_reduce_then_scan(count);
+    auto pass = [&](const auto &src, int p, int kind, double bytes) {
+        using S = typename std::decay<decltype(src)>::type;
+        const uint32_t nt = src.tiles();
+        if (w.prof) w.prof->begin(kind);
+        if (rts) {
+            const uint32_t tb = 1024;
+            const uint32_t nb = (nt + tb - 1) / tb;
+            w.tcnt.ensure((size_t)nt * kRadix * sizeof(uint32_t), 1.25);
+            w.toff.ensure((size_t)nt * kRadix * sizeof(uint64_t), 1.25);
+            w.bsum.ensure((size_t)nb * kRadix * sizeof(uint64_t), 1.25);
+            hipLaunchKernelGGL(tile_count_kernel<S>, dim3(nt), dim3(kBlock), 0, w.stream, src, pd.shift[p],
+                               pd.mask[p], w.tcnt.as<uint32_t>());
+            hipLaunchKernelGGL(tile_colsum_kernel, dim3(nb), dim3(kBlock), 0, w.stream, w.tcnt.as<const uint32_t>(),
+                               nt, tb, w.bsum.as<uint64_t>());
+            hipLaunchKernelGGL(bsum_scan_kernel, dim3(1), dim3(kBlock), 0, w.stream, w.bsum.as<uint64_t>(), nb,
+                               base + p * kRadix);
+            hipLaunchKernelGGL(tile_offset_kernel, dim3(nb), dim3(kBlock), 0, w.stream, w.tcnt.as<const uint32_t>(),
+                               nt, tb, w.bsum.as<const uint64_t>(), w.toff.as<uint64_t>());
+            hipLaunchKernelGGL((onesweep_kernel<S, false>), dim3(nt), dim3(kBlock), 0, w.stream, src, cur_out, count,
+                               pd.shift[p], pd.mask[p], base + p * kRadix, w.status.as<uint64_t>(), w.tickets() + p,
+                               0u, w.err(), w.toff.as<const uint64_t>());
+        } else {
+            const uint32_t epoch = w.next_epoch();
+            hipLaunchKernelGGL((onesweep_kernel<S, true>), dim3(nt), dim3(kBlock), 0, w.stream, src, cur_out, count,
+                               pd.shift[p], pd.mask[p], base + p * kRadix, w.status.as<uint64_t>(), w.tickets() + p,
+                               epoch, w.err(), (const uint64_t *)nullptr);
+        }
+        CG_HIP(hipGetLastError());
+        if (w.prof) w.prof->end(kind, bytes, (double)count);
+    };
     for (int q = 0; q < nkeep; ++q) {
         const int p = keep[q];
-        const uint32_t epoch = w.next_epoch();
         if (q == 0) {
-            const int kind = fused_first ? K_SORT_FUSED : K_SORT;
-            if (w.prof) w.prof->begin(kind);
-            hipLaunchKernelGGL(onesweep_kernel<Src>, dim3(t0), dim3(kBlock), 0, w.stream, first_src,
-                               cur_out, count, pd.shift[p], pd.mask[p], base + p * kRadix,
-                               w.status.as<uint64_t>(), w.tickets() + p, epoch, w.err());
-            CG_HIP(hipGetLastError());
-            if (w.prof) w.prof->end(kind, first_read_bytes + kb * (double)count, (double)count);
+            pass(first_src, p, fused_first ? K_SORT_FUSED : K_SORT, first_read_bytes + kb * (double)count);
         } else {
             const ArraySrcT<K> s{cur_in, count};
-            if (w.prof) w.prof->begin(K_SORT);
-            hipLaunchKernelGGL(onesweep_kernel<ArraySrcT<K>>, dim3(s.tiles()), dim3(kBlock), 0, w.stream,
-                               s, cur_out, count, pd.shift[p], pd.mask[p], base + p * kRadix,
-                               w.status.as<uint64_t>(), w.tickets() + p, epoch, w.err());
-            CG_HIP(hipGetLastError());
-            if (w.prof) w.prof->end(K_SORT, 2.0 * kb * (double)count, (double)count);
+            pass(s, p, K_SORT, 2.0 * kb * (double)count);
         }
         cur_in = cur_out;
         cur_out = (cur_out == buf0) ? buf1 : buf0;

@@ -234,7 +234,8 @@ void DevBuf::release() {
 
 void PipeWork::init(hipStream_t s) {
     stream = s;
-    for (DevBuf *b : {&hist, &base, &small, &status, &bounds, &tile_cnt, &tile_off, &kill}) b->stream = s;
+    for (DevBuf *b : {&hist, &base, &small, &status, &bounds, &tile_cnt, &tile_off, &kill, &tcnt, &toff, &bsum})
+        b->stream = s;
     hist.ensure(kMaxPasses * 256 * sizeof(uint64_t));
     base.ensure(kMaxPasses * 256 * sizeof(uint64_t));
     small.ensure(32 * sizeof(uint32_t) + 4 * sizeof(uint32_t) + 8 * sizeof(uint64_t) + 256);

@@ -2,6 +2,7 @@
 of the same operation, element by element (bit-exact: integer work)."""
 
 import itertools
+import os
 
 import numpy as np
 import pytest
@@ -131,3 +132,43 @@ def test_copy_kernel_copies(nbytes, rng):
     T.copy(src, dst, repeats=2)
     torch.cuda.synchronize()
     assert torch.equal(src, dst)
+
+
+@pytest.fixture
+def rts_min():
+    old = os.environ.get("CG_SORT_RTS_MIN")
+
+    def set_(v):
+        os.environ["CG_SORT_RTS_MIN"] = str(v)
+
+    yield set_
+    if old is None:
+        os.environ.pop("CG_SORT_RTS_MIN", None)
+    else:
+        os.environ["CG_SORT_RTS_MIN"] = old
+
+
+@pytest.mark.parametrize("mode", ["reduce_then_scan", "lookback"])
+@pytest.mark.parametrize("count,lo,hi", [(1, 0, 64), (4097, 4, 48), (8193 * 3 + 5, 0, 64), (300001, 4, 44),
+                                         ((1 << 20) + 37, 8, 40)])
+def test_sort_both_pass_modes(mode, count, lo, hi, rng, rts_min):
+    rts_min(1 if mode == "reduce_then_scan" else 0)
+    keys = rng.integers(0, 1 << 63, size=count, dtype=np.int64).astype(np.uint64)
+    keys[: count // 3] = keys[0]  # a heavy repeat
+    d = T.from_u64(keys)
+    T.sort(d, lo, hi)
+    got = T.to_u64(d)
+    field = (keys >> np.uint64(lo)) & np.uint64((1 << (hi - lo)) - 1) if hi - lo < 64 else keys
+    exp = keys[np.argsort(field, kind="stable")]
+    assert np.array_equal(got, exp)
+
+
+@pytest.mark.parametrize("fam,n", [("pancake", 9), ("lrx", 10), ("all_transpositions", 8)])
+def test_growth_with_reduce_then_scan(fam, n, rts_min, oracle_c):
+    from paper_2509_19162_amd import api
+
+    rts_min(1)
+    gens = I.family(fam, n)
+    exp = oracle_c.growth(n, gens, max_layers=512)[0]
+    assert api.growth_ex(n, gens, max_layers=512).sizes == exp
+    assert api.growth_ex(n, gens, max_layers=512, packed_sort=True).sizes == exp
