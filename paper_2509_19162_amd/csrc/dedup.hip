@@ -49,6 +49,7 @@ __device__ __forceinline__ uint32_t pad(uint32_t i) { return i + (i >> 4); }
 // form and a candidate back into a layer key; both preserve order.
 struct PackedKeys {
     using K = uint64_t;
+    using Ref = uint64_t;  // reference layers as stored
     int n;
     __device__ __forceinline__ K from_layer(uint64_t x) const { return x; }
     __device__ __forceinline__ uint64_t to_layer(K x) const { return x; }
@@ -56,8 +57,19 @@ struct PackedKeys {
 template <int N>
 struct RankedKeys {
     using K = uint32_t;
+    using Ref = uint64_t;
     int n;
     __device__ __forceinline__ K from_layer(uint64_t x) const { return perm_rank_t<N>(x); }
+    __device__ __forceinline__ uint64_t to_layer(K x) const { return perm_unrank_t<N>(x); }
+};
+// Reference layers given by their ranks (kept beside the packed layers):
+// no ranking in the set difference.
+template <int N>
+struct RankedRefs {
+    using K = uint32_t;
+    using Ref = uint32_t;
+    int n;
+    __device__ __forceinline__ K from_layer(uint32_t x) const { return x; }
     __device__ __forceinline__ uint64_t to_layer(K x) const { return perm_unrank_t<N>(x); }
 };
 
@@ -66,13 +78,13 @@ struct RankedKeys {
 // searches of neighbouring tiles share their upper levels in the caches.
 template <class P>
 __global__ __launch_bounds__(256) void tile_bounds_kernel(
-    P pol, const typename P::K *__restrict__ S, uint64_t C, const uint64_t *__restrict__ A, uint64_t na,
-    const uint64_t *__restrict__ B, uint64_t nb, uint64_t *__restrict__ bounds, uint32_t ntiles) {
+    P pol, const typename P::K *__restrict__ S, uint64_t C, const typename P::Ref *__restrict__ A, uint64_t na,
+    const typename P::Ref *__restrict__ B, uint64_t nb, uint64_t *__restrict__ bounds, uint32_t ntiles) {
     using K = typename P::K;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 4 * ntiles) return;
     const uint32_t t = i >> 2, w = i & 3u;
-    const uint64_t *R = w < 2 ? A : B;
+    const typename P::Ref *R = w < 2 ? A : B;
     const uint64_t nr = w < 2 ? na : nb;
     const bool upper = (w & 1u) != 0;
     const uint64_t end = ((uint64_t)t + 1) * kTile < C ? ((uint64_t)t + 1) * kTile : C;
@@ -99,7 +111,7 @@ __global__ __launch_bounds__(256) void tile_bounds_kernel(
 // references would fall to the one or two blocks whose key range covers them.
 template <class P>
 __global__ __launch_bounds__(256) void mark_refs_kernel(P pol, const typename P::K *__restrict__ S, uint64_t C,
-                                                        const uint64_t *__restrict__ R, uint64_t nr,
+                                                        const typename P::Ref *__restrict__ R, uint64_t nr,
                                                         uint8_t *__restrict__ kill) {
     using K = typename P::K;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -119,8 +131,8 @@ __global__ __launch_bounds__(256) void mark_refs_kernel(P pol, const typename P:
 
 template <class P>
 __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
-    P pol, const typename P::K *__restrict__ S, uint64_t C, const uint64_t *__restrict__ A, uint64_t na,
-    const uint64_t *__restrict__ B, uint64_t nb, const uint64_t *__restrict__ bounds,
+    P pol, const typename P::K *__restrict__ S, uint64_t C, const typename P::Ref *__restrict__ A, uint64_t na,
+    const typename P::Ref *__restrict__ B, uint64_t nb, const uint64_t *__restrict__ bounds,
     const uint8_t *__restrict__ gkill, typename P::K *__restrict__ tmp, uint32_t *__restrict__ cnt) {
     using K = typename P::K;
     __shared__ K s_keys[kTile + kTile / 16];
@@ -159,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
     // one looks itself up in the sorted tile (12 LDS probes) and marks the
     // first equal candidate; later copies of a key are dropped as repeats.
     for (int r = 0; r < 2; ++r) {
-        const uint64_t *R = r == 0 ? A : B;
+        const typename P::Ref *R = r == 0 ? A : B;
         const uint64_t lo = bnd[2 * r], hi = bnd[2 * r + 1];
         for (uint64_t i = lo + tid; i < hi; i += kBlock) {
             const K key = pol.from_layer(R[i]);
@@ -265,22 +277,28 @@ __global__ __launch_bounds__(kScanBlock) void count_scan_kernel(
     }
 }
 
-// Phase 3: move each tile's survivors to their final place.
+// Phase 3: move each tile's survivors to their final place (and, for
+// ranked candidates, their ranks to rank_out when it is given).
 template <class P>
 __global__ __launch_bounds__(kBlock) void gather_kernel(P pol, const typename P::K *__restrict__ tmp,
                                                         const uint32_t *__restrict__ cnt,
                                                         const uint64_t *__restrict__ off,
                                                         uint64_t *__restrict__ out, uint64_t out_cap,
+                                                        uint32_t *__restrict__ rank_out,
                                                         uint32_t *__restrict__ err) {
     const uint32_t tile = blockIdx.x;
     const uint32_t c = cnt[tile];
     const uint64_t o = off[tile];
     const uint64_t base = (uint64_t)tile * kTile;
     for (uint32_t i = threadIdx.x; i < c; i += kBlock) {
-        if (o + i < out_cap)
-            out[o + i] = pol.to_layer(tmp[base + i]);
-        else
+        if (o + i < out_cap) {
+            const typename P::K v = tmp[base + i];
+            out[o + i] = pol.to_layer(v);
+            if constexpr (sizeof(typename P::K) == 4)
+                if (rank_out) rank_out[o + i] = v;
+        } else {
             atomicOr(err, 4u);  // more survivors than the output holds
+        }
     }
 }
 
@@ -294,8 +312,8 @@ uint64_t dedup_status_words(uint64_t C) {
 namespace {
 
 template <class P>
-void dedup_count_impl(P pol, const typename P::K *sorted, uint64_t C, const uint64_t *a, uint64_t na,
-                      const uint64_t *b, uint64_t nb, typename P::K *tmp, uint64_t *d_count, PipeWork &w) {
+void dedup_count_impl(P pol, const typename P::K *sorted, uint64_t C, const typename P::Ref *a, uint64_t na,
+                      const typename P::Ref *b, uint64_t nb, typename P::K *tmp, uint64_t *d_count, PipeWork &w) {
     uint32_t *ticket = w.tickets() + 31;
     // clears the ticket and the output count (a kernel, not a memset, so the
     // sequence stays valid inside a captured graph)
@@ -347,12 +365,13 @@ void dedup_count_impl(P pol, const typename P::K *sorted, uint64_t C, const uint
 }
 
 template <class P>
-void dedup_gather_impl(P pol, const typename P::K *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w) {
+void dedup_gather_impl(P pol, const typename P::K *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w,
+                       uint32_t *rank_out = nullptr) {
     if (!w.dedup_tiles) return;
     if (w.prof) w.prof->begin(K_DEDUP);
     hipLaunchKernelGGL(gather_kernel<P>, dim3(w.dedup_tiles), dim3(kBlock), 0, w.stream, pol, tmp,
                        w.tile_cnt.as<const uint32_t>(), w.tile_off.as<const uint64_t>(), out, out_cap,
-                       w.err());
+                       rank_out, w.err());
     CG_HIP(hipGetLastError());
     if (w.prof) w.prof->end(K_DEDUP, 0, 0);
 }
@@ -377,8 +396,19 @@ void launch_dedup_count_ranked(int n, const uint32_t *sorted, uint64_t C, const 
     });
 }
 
-void launch_dedup_gather_ranked(int n, const uint32_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w) {
-    with_rank_n(n, [&](auto NN) { dedup_gather_impl(RankedKeys<decltype(NN)::value>{n}, tmp, out, out_cap, w); });
+void launch_dedup_gather_ranked(int n, const uint32_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w,
+                                uint32_t *rank_out) {
+    with_rank_n(n, [&](auto NN) {
+        dedup_gather_impl(RankedKeys<decltype(NN)::value>{n}, tmp, out, out_cap, w, rank_out);
+    });
+}
+
+void launch_dedup_count_ranked_refs(int n, const uint32_t *sorted, uint64_t C, const uint32_t *a, uint64_t na,
+                                    const uint32_t *b, uint64_t nb, uint32_t *tmp, uint64_t *d_count,
+                                    PipeWork &w) {
+    with_rank_n(n, [&](auto NN) {
+        dedup_count_impl(RankedRefs<decltype(NN)::value>{n}, sorted, C, a, na, b, nb, tmp, d_count, w);
+    });
 }
 
 void launch_dedup(const uint64_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,

@@ -114,7 +114,7 @@ Engine::Engine(hipStream_t user_stream) {
     }
     w_.init(stream_);
     for (DevBuf *b : {&gsel_, &cand0_, &cand1_, &lay_[0], &lay_[1], &lay_[2], &arena_, &stage_, &chunk_hist_, &vis_[0],
-                      &vis_[1]})
+                      &vis_[1], &rk_[0], &rk_[1], &rk_[2]})
         b->stream = stream_;
     prof_.stream = stream_;
     CG_HIP(hipHostMalloc((void **)&host_small_, 64, hipHostMallocDefault));
@@ -125,7 +125,7 @@ Engine::~Engine() {
     if (host_small_) (void)hipHostFree(host_small_);
     // buffers go back to the device cache while their stream still exists
     for (DevBuf *b : {&gsel_, &cand0_, &cand1_, &lay_[0], &lay_[1], &lay_[2], &arena_, &stage_, &chunk_hist_,
-                      &vis_[0], &vis_[1]})
+                      &vis_[0], &vis_[1], &rk_[0], &rk_[1], &rk_[2]})
         b->release();
     for (DevBuf *b : {&w_.hist, &w_.base, &w_.small, &w_.status, &w_.bounds, &w_.tile_cnt, &w_.tile_off,
                       &w_.kill, &w_.tcnt, &w_.toff, &w_.bsum})
@@ -381,6 +381,18 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
         }
     }
     const bool ranked = perm_start && !(spec.flags & CG_PACKED_SORT);
+    // Ranked runs keep the 32-bit ranks of layers d-1 and d beside the packed
+    // layers (written by the gather), so the set difference does not rank its
+    // reference keys again. A layer from the chunked path has none; the next
+    // two steps then rank the packed layers on the fly.
+    int kp = 0, kc = 1, kn = 2;
+    bool rk_cur = false, rk_prev = false;
+    if (ranked && !directed) {
+        const uint32_t r0 = perm_rank(key0, n);
+        rk_[kc].ensure(64);
+        CG_HIP(hipMemcpyAsync(rk_[kc].p, &r0, sizeof r0, hipMemcpyHostToDevice, stream_));
+        rk_cur = rk_prev = true;  // layer -1 is empty
+    }
     int rank_bits = 0;
     while (rank_bits < 32 && (1ull << rank_bits) < spec.orbit_bound) ++rank_bits;
     int layers = 1;
@@ -451,6 +463,7 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
         const uint64_t *Rb = directed ? nullptr : Lp;
         const uint64_t nb = directed ? 0 : np;
         uint64_t N = 0;
+        bool rk_next = false;
         if (chunked) {
             uint64_t *dst = keep_all ? out : nullptr;
             N = run_chunked(ranked, n, Ld, F, Ra, na, Rb, nb, k, cap, rank_bits, bit_lo, bit_hi, dst, out_cap, room,
@@ -462,14 +475,25 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             uint32_t *c0 = cand0_.as<uint32_t>(), *c1 = cand1_.as<uint32_t>();
             const uint32_t *sorted = expand_rank_sort(n, Ld, F, gsel_.as<GenSel>(), k, c0, c1, rank_bits, w_);
             uint32_t *scratch = sorted == c0 ? c1 : c0;
-            launch_dedup_count_ranked(n, sorted, C, Ra, na, Rb, nb, scratch, w_.counter(), w_);
+            const bool by_rank = !directed && rk_cur && rk_prev;
+            if (by_rank)
+                launch_dedup_count_ranked_refs(n, sorted, C, rk_[kc].as<const uint32_t>(), F,
+                                               rk_[kp].as<const uint32_t>(), np, scratch, w_.counter(), w_);
+            else
+                launch_dedup_count_ranked(n, sorted, C, Ra, na, Rb, nb, scratch, w_.counter(), w_);
             N = read_counter();
             if (N > C || N > room) throw Error(CG_E_DEVICE, "layer size out of range (device error)");
             if (!keep_all) {
                 lay_[in].ensure(std::max<uint64_t>(N, 1) * sizeof(uint64_t), 1.25);
                 out = lay_[in].as<uint64_t>();
             }
-            launch_dedup_gather_ranked(n, scratch, out, keep_all ? out_cap : N, w_);
+            uint32_t *rank_out = nullptr;
+            if (!directed) {
+                rk_[kn].ensure(std::max<uint64_t>(N, 1) * sizeof(uint32_t), 1.25);
+                rank_out = rk_[kn].as<uint32_t>();
+            }
+            launch_dedup_gather_ranked(n, scratch, out, keep_all ? out_cap : N, w_, rank_out);
+            rk_next = rank_out != nullptr;
         } else {
             const uint64_t *sorted = expand_sort(Ld, F, gsel_.as<GenSel>(), k, cand0_.as<uint64_t>(),
                                                  cand1_.as<uint64_t>(), bit_lo, bit_hi, w_);
@@ -510,6 +534,14 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             ip = ic;
             ic = in;
             in = t;
+        }
+        {
+            const int t = kp;
+            kp = kc;
+            kc = kn;
+            kn = t;
+            rk_prev = rk_cur;
+            rk_cur = rk_next;
         }
         np = F;
         F = N;
