@@ -37,16 +37,21 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-// Keys per thread: 16 for 64-bit keys (4096-key tiles), 32 for 32-bit keys
-// (8192-key tiles). Both fill 32 KB of LDS per tile; the longer tiles of
-// 32-bit keys halve the per-tile fixed cost (look-back, digit scan).
+// Keys per thread: 16 for 64-bit keys (256 threads, 4096-key tiles), 32 for
+// 32-bit keys (512 threads, 16384-key tiles). Longer tiles mean fewer tiles
+// chained through the look-back for the same keys in flight.
 #ifndef CG_SORT_IPT32
 #define CG_SORT_IPT32 32
+#endif
+#ifndef CG_SORT_BLOCK32
+#define CG_SORT_BLOCK32 512
 #endif
 template <class K>
 struct TileOf {
     static constexpr int ipt = sizeof(K) == 4 ? CG_SORT_IPT32 : 16;
-    static constexpr int tile = kBlock * ipt;
+    static constexpr int block = sizeof(K) == 4 ? CG_SORT_BLOCK32 : kBlock;  // threads of a sort tile
+    static constexpr int waves = block / kWave;
+    static constexpr int tile = block * ipt;
     static constexpr int wave_seg = kWave * ipt;  // keys owned by one wave
 };
 constexpr int kTile = TileOf<uint64_t>::tile;  // the shortest tile: sizes look-back state
@@ -266,7 +271,7 @@ __global__ void clear_kernel(unsigned long long *__restrict__ a, uint32_t na,
 // decoupled look-back. Lookback = false: tile = block index and each
 // tile's digit offsets come precomputed in tile_off (reduce-then-scan).
 template <class Src, bool Lookback>
-__global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
+__global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void onesweep_kernel(
     Src src, typename Src::Key *__restrict__ out, uint64_t total, int shift, uint32_t dmask,
     const unsigned long long *__restrict__ digit_base, uint64_t *__restrict__ status,
     uint32_t *__restrict__ ticket, uint32_t epoch, uint32_t *__restrict__ err,
@@ -275,16 +280,19 @@ __global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
     constexpr int kIpt = TileOf<K>::ipt;
     constexpr int kTileK = TileOf<K>::tile;
     constexpr int kWaveSeg = TileOf<K>::wave_seg;
+    constexpr int kBlk = TileOf<K>::block;
+    constexpr int kWv = TileOf<K>::waves;
+    static_assert(kBlk >= kRadix, "one thread per digit in the look-back");
     __shared__ __align__(16) K s_keys[kTileK];
-    __shared__ uint32_t s_cnt[kWaves][kRadix];
+    __shared__ uint32_t s_cnt[kWv][kRadix];
     __shared__ uint64_t s_gstart[kRadix];
     __shared__ uint32_t s_lstart[kRadix];
-    __shared__ uint32_t s_scan[kWaves];
+    __shared__ uint32_t s_scan[kWv];
     __shared__ uint32_t s_tile;
 
     // the digit masks of the ranking live in s_keys until the scatter
-    uint64_t(*s_match)[kWaves][kRadix] = reinterpret_cast<uint64_t(*)[kWaves][kRadix]>(s_keys);
-    static_assert(kRows * kWaves * kRadix * sizeof(uint64_t) <= kTileK * sizeof(K),
+    uint64_t(*s_match)[kWv][kRadix] = reinterpret_cast<uint64_t(*)[kWv][kRadix]>(s_keys);
+    static_assert(kRows * kWv * kRadix * sizeof(uint64_t) <= kTileK * sizeof(K),
                   "match words fit in the key tile");
     static_assert(kIpt % kRows == 0, "rows per group divide the rows per thread");
 
@@ -293,8 +301,8 @@ __global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
     const uint32_t wave = tid / kWave;
 
     if (Lookback && tid == 0) s_tile = atomicAdd(ticket, 1u);
-    for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_cnt[0][0])[i] = 0;
-    for (int i = tid; i < kRows * kWaves * kRadix; i += kBlock) (&s_match[0][0][0])[i] = 0;
+    for (int i = tid; i < kWv * kRadix; i += kBlk) (&s_cnt[0][0])[i] = 0;
+    for (int i = tid; i < kRows * kWv * kRadix; i += kBlk) (&s_match[0][0][0])[i] = 0;
     __syncthreads();
     const uint32_t tile = Lookback ? s_tile : blockIdx.x;
     const auto T = src.tile(tile);
@@ -369,12 +377,12 @@ __global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
     }
     __syncthreads();
 
-    // thread tid owns digit tid: wave prefix, tile count, look-back
-    {
+    // thread tid < 256 owns digit tid: wave prefix, tile count, look-back
+    uint32_t run = 0;
+    if (tid < (uint32_t)kRadix) {
         const uint32_t d = tid;
-        uint32_t run = 0;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
+        for (int w = 0; w < kWv; ++w) {
             const uint32_t c = s_cnt[w][d];
             s_cnt[w][d] = run;
             run += c;
@@ -395,12 +403,16 @@ __global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
         } else {
             s_gstart[d] = tile_off[(uint64_t)tile * kRadix + d];
         }
+    }
+    {
         uint32_t tot;
-        const uint32_t lstart = block_excl_scan<kWaves>(run, s_scan, &tot);
-        s_lstart[d] = lstart;
-        // each wave's slot for this digit in the tile-sorted order
+        const uint32_t lstart = block_excl_scan<kWv>(run, s_scan, &tot);  // every thread takes part
+        if (tid < (uint32_t)kRadix) {
+            s_lstart[tid] = lstart;
+            // each wave's slot for this digit in the tile-sorted order
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) s_cnt[w][d] += lstart;
+            for (int w = 0; w < kWv; ++w) s_cnt[w][tid] += lstart;
+        }
     }
     __syncthreads();
 
@@ -411,7 +423,7 @@ __global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
     }
     __syncthreads();
 
-    for (uint32_t i = tid; i < nvalid; i += kBlock) {
+    for (uint32_t i = tid; i < nvalid; i += kBlk) {
         const K k = s_keys[i];
         const uint32_t d = (uint32_t)(k >> shift) & dmask;
         const uint64_t gpos = s_gstart[d] + (i - s_lstart[d]);
@@ -426,14 +438,16 @@ __global__ __launch_bounds__(kBlock) CG_SORT_ATTR void onesweep_kernel(
 // Same tiles (and the same load pattern) as the scatter pass; only the real
 // keys of a short tile are counted.
 template <class Src>
-__global__ __launch_bounds__(kBlock) void tile_count_kernel(Src src, int shift, uint32_t dmask,
-                                                            uint32_t *__restrict__ tcnt) {
+__global__ __launch_bounds__(TileOf<typename Src::Key>::block) void tile_count_kernel(Src src, int shift,
+                                                                                     uint32_t dmask,
+                                                                                     uint32_t *__restrict__ tcnt) {
     using K = typename Src::Key;
     constexpr int kIpt = TileOf<K>::ipt;
     constexpr int kWaveSeg = TileOf<K>::wave_seg;
+    constexpr int kBlk = TileOf<K>::block;
     __shared__ uint32_t s_h[kRadix];
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    s_h[tid] = 0;
+    for (uint32_t i = tid; i < (uint32_t)kRadix; i += kBlk) s_h[i] = 0;
     __syncthreads();
     const auto T = src.tile(blockIdx.x);
     uint32_t cur = 0, run = 0;
@@ -453,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void tile_count_kernel(Src src, int shift, 
     }
     if (run) atomicAdd(&s_h[cur], run);
     __syncthreads();
-    tcnt[(uint64_t)blockIdx.x * kRadix + tid] = s_h[tid];
+    if (tid < (uint32_t)kRadix) tcnt[(uint64_t)blockIdx.x * kRadix + tid] = s_h[tid];
 }
 
 // Sums of each digit's counts over runs of `tb` tiles (one block per run).
@@ -591,7 +605,8 @@ typename Src::Key *run_sort(const Src &first_src, uint64_t count, typename Src::
             w.tcnt.ensure((size_t)nt * kRadix * sizeof(uint32_t), 1.25);
             w.toff.ensure((size_t)nt * kRadix * sizeof(uint64_t), 1.25);
             w.bsum.ensure((size_t)nb * kRadix * sizeof(uint64_t), 1.25);
-            hipLaunchKernelGGL(tile_count_kernel<S>, dim3(nt), dim3(kBlock), 0, w.stream, src, pd.shift[p],
+            hipLaunchKernelGGL(tile_count_kernel<S>, dim3(nt), dim3(TileOf<typename S::Key>::block), 0, w.stream, src,
+                               pd.shift[p],
                                pd.mask[p], w.tcnt.as<uint32_t>());
             hipLaunchKernelGGL(tile_colsum_kernel, dim3(nb), dim3(kBlock), 0, w.stream, w.tcnt.as<const uint32_t>(),
                                nt, tb, w.bsum.as<uint64_t>());
@@ -599,12 +614,14 @@ typename Src::Key *run_sort(const Src &first_src, uint64_t count, typename Src::
                                base + p * kRadix);
             hipLaunchKernelGGL(tile_offset_kernel, dim3(nb), dim3(kBlock), 0, w.stream, w.tcnt.as<const uint32_t>(),
                                nt, tb, w.bsum.as<const uint64_t>(), w.toff.as<uint64_t>());
-            hipLaunchKernelGGL((onesweep_kernel<S, false>), dim3(nt), dim3(kBlock), 0, w.stream, src, cur_out, count,
+            hipLaunchKernelGGL((onesweep_kernel<S, false>), dim3(nt), dim3(TileOf<typename S::Key>::block), 0,
+                               w.stream, src, cur_out, count,
                                pd.shift[p], pd.mask[p], base + p * kRadix, w.status.as<uint64_t>(), w.tickets() + p,
                                0u, w.err(), w.toff.as<const uint64_t>());
         } else {
             const uint32_t epoch = w.next_epoch();
-            hipLaunchKernelGGL((onesweep_kernel<S, true>), dim3(nt), dim3(kBlock), 0, w.stream, src, cur_out, count,
+            hipLaunchKernelGGL((onesweep_kernel<S, true>), dim3(nt), dim3(TileOf<typename S::Key>::block), 0,
+                               w.stream, src, cur_out, count,
                                pd.shift[p], pd.mask[p], base + p * kRadix, w.status.as<uint64_t>(), w.tickets() + p,
                                epoch, w.err(), (const uint64_t *)nullptr);
         }
