@@ -1,5 +1,10 @@
 // Serving: a request queue with continuous batching (cg_queue_*).
 //
+// Cheap jobs (a permutation start, n! * k <= 2^22 candidates) go to a
+// small-job lane: each launch of the one-workgroup-per-job engine takes
+// every such job queued at that moment, and jobs that arrive meanwhile
+// join the next launch.
+//
 // Client threads submit growth jobs; an engine thread admits queued jobs
 // while their estimated device footprint fits the budget, adds them into
 // free slots of a shared group (job-tagged keys, see batch_kernels.hip) at
@@ -29,6 +34,7 @@ namespace cg {
 namespace {
 
 constexpr int kSharedN = 13;  // 4*13 state bits + 12 tag bits = 64
+constexpr uint64_t kSmallLaneWork = 1ull << 22;  // n! * k candidates at most
 constexpr uint64_t kLargeOrbit = 1ull << 21;
 
 // Upper estimate of a job's peak device bytes: the largest layer is taken
@@ -63,17 +69,19 @@ struct cg_queue {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::thread engine;
+    std::thread small_lane;
     std::vector<std::thread> big_lanes;
     int big_running = 0;
     bool stopping = false;
     uint64_t next_ticket = 1;
     uint64_t budget = 0, in_use = 0;
-    std::deque<cg::QueueReq *> queued, big_queued;
+    std::deque<cg::QueueReq *> queued, big_queued, small_queued;
     std::map<uint64_t, std::unique_ptr<cg::QueueReq>> reqs;
     std::string fatal;  // non-empty once the engine failed
 
     void engine_loop();
     void big_loop();
+    void small_loop();
     void retire(cg::QueueReq *r, int status);
 };
 
@@ -203,6 +211,65 @@ void cg_queue::big_loop() {
     }
 }
 
+// Small jobs (n <= 10, a permutation start): each launch of the small-job
+// engine runs every such job queued at that moment, one workgroup per job;
+// jobs that arrive meanwhile join the next launch. A job that has started
+// runs to completion (a cancel then has no effect).
+void cg_queue::small_loop() {
+    hipStream_t stream = nullptr;
+    std::unique_ptr<cg::WgRunner> runner;
+    try {
+        CG_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        runner.reset(new cg::WgRunner(stream));
+        for (;;) {
+            std::vector<cg::QueueReq *> batch;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] { return stopping || !small_queued.empty(); });
+                if (small_queued.empty()) break;
+                while (!small_queued.empty()) {
+                    cg::QueueReq *r = small_queued.front();
+                    small_queued.pop_front();
+                    if (r->cancel || stopping) {
+                        r->res->t_submit = r->t_submit;
+                        r->res->t_admit = r->res->t_done = cg::now_seconds();
+                        retire(r, CG_E_CANCELLED);
+                        continue;
+                    }
+                    r->state = 1;
+                    in_use += r->bytes;
+                    batch.push_back(r);
+                }
+            }
+            if (batch.empty()) continue;
+            std::vector<cg::WgItem> items;
+            for (auto *r : batch) items.push_back({&r->spec, r->res});
+            int status = CG_OK;
+            try {
+                cg::WgTuning t;
+                runner->run(items, t, 0.0);
+            } catch (const cg::Error &e) {
+                status = e.code;
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            for (auto *r : batch) {
+                r->res->t_submit = r->t_submit;
+                retire(r, status == CG_OK ? r->res->status : status);
+            }
+        }
+    } catch (const std::exception &e) {
+        std::lock_guard<std::mutex> lk(mu);
+        fatal = e.what();
+        for (auto *r : small_queued) retire(r, CG_E_DEVICE);
+        small_queued.clear();
+    }
+    runner.reset();
+    if (stream) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipStreamDestroy(stream);
+    }
+}
+
 extern "C" {
 
 cg_queue_t *cg_queue_create(const cg_queue_opts_t *opts) {
@@ -213,6 +280,7 @@ cg_queue_t *cg_queue_create(const cg_queue_opts_t *opts) {
         CG_HIP(hipMemGetInfo(&free_b, &total_b));
         q->budget = q->opts.hbm_budget_bytes ? q->opts.hbm_budget_bytes : (uint64_t)(0.6 * (double)free_b);
         q->engine = std::thread([p = q.get()] { p->engine_loop(); });
+        q->small_lane = std::thread([p = q.get()] { p->small_loop(); });
         const int lanes = q->opts.large_lanes > 0 ? std::min(q->opts.large_lanes, 8) : 2;
         for (int i = 0; i < lanes; ++i) q->big_lanes.emplace_back([p = q.get()] { p->big_loop(); });
         return q.release();
@@ -238,9 +306,17 @@ int cg_queue_submit(cg_queue_t *q, const cg_job_t *job, cg_result_t *res_slot, u
     std::lock_guard<std::mutex> lk(q->mu);
     if (!q->fatal.empty() || q->stopping) return CG_E_DEVICE;
     const int max_q = q->opts.max_queued > 0 ? q->opts.max_queued : 65536;
-    if ((int)(q->queued.size() + q->big_queued.size()) >= max_q) return CG_E_BUSY;
+    if ((int)(q->queued.size() + q->big_queued.size() + q->small_queued.size()) >= max_q) return CG_E_BUSY;
     r->ticket = q->next_ticket++;
-    r->big = r->spec.n > cg::kSharedN || r->spec.orbit_bound > cg::kLargeOrbit || r->bytes > q->budget / 4;
+    // cheap jobs only: one workgroup runs the whole job, and a launch lasts
+    // as long as its slowest job
+    uint64_t states = 1;
+    for (int i = 2; i <= r->spec.n; ++i) states *= (uint64_t)i;
+    const bool small = r->spec.n <= cg::kWgMaxN && cg::wg_eligible(r->spec) &&
+                       states * (uint64_t)std::max(1, r->spec.k) <= cg::kSmallLaneWork;
+    if (small) r->bytes = 3 * ((states + 31) / 32) * 4;  // the job's three bitmaps
+    r->big = !small &&
+             (r->spec.n > cg::kSharedN || r->spec.orbit_bound > cg::kLargeOrbit || r->bytes > q->budget / 4);
     // large permutation jobs from n = 12 run in the bitmask engine: 3 bits
     // per state of S_n instead of 8-byte layers and candidate arrays (an
     // S_13 job holds 2.3 GB there); results are the same
@@ -255,6 +331,8 @@ int cg_queue_submit(cg_queue_t *q, const cg_job_t *job, cg_result_t *res_slot, u
     q->reqs[r->ticket] = std::move(r);
     if (p->big) {
         q->big_queued.push_back(p);
+    } else if (small) {
+        q->small_queued.push_back(p);
     } else {
         q->queued.push_back(p);
     }
@@ -305,6 +383,7 @@ void cg_queue_destroy(cg_queue_t *q) {
         q->cv_work.notify_all();
     }
     if (q->engine.joinable()) q->engine.join();
+    if (q->small_lane.joinable()) q->small_lane.join();
     for (auto &t : q->big_lanes)
         if (t.joinable()) t.join();
     delete q;
