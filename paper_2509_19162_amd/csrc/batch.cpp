@@ -348,6 +348,20 @@ void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_
     }
     const bool tune = opts && opts->tune;
     const int wg_max_n = default_wg_max_n();
+    // One workgroup runs a whole job, so a job far larger than its share of
+    // the launch would leave the rest of the device idle at the end: such
+    // jobs (work n! * k above 1/64 of all small-job work, and above 2^22)
+    // go to tagged groups, which spread one job over the whole device.
+    auto work = [](const JobSpec &sp) {
+        uint64_t w = (uint64_t)std::max(1, sp.k);
+        for (int i = 2; i <= sp.n; ++i) w *= (uint64_t)i;
+        return w;
+    };
+    double wg_total = 0;
+    for (auto &kv : by_n)
+        for (auto &it : kv.second)
+            if (wg_eligible(it.spec)) wg_total += (double)work(it.spec);
+    const double heavy = std::max((double)(1ull << 22), wg_total / 64.0);
     try {
         std::vector<WgItem> wg_items;
         WgTuning wg_t;
@@ -360,7 +374,7 @@ void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_
             std::vector<Item> items;
             std::vector<Item *> wg_ok;
             for (auto &it : all) {
-                if (wg_eligible(it.spec))
+                if (wg_eligible(it.spec) && (!it.spec.inverse_closed || (double)work(it.spec) <= heavy))
                     wg_ok.push_back(&it);
                 else if (!it.spec.inverse_closed) {
                     cg_result_t *r = &results[it.idx];

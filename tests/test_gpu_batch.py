@@ -90,3 +90,14 @@ def test_batch_workload_4096_matches_oracle():
     exp = d["batch_4096"]["sizes"]
     bad = [i for i, r in enumerate(res) if r.sizes != exp[i]]
     assert not bad, bad[:10]
+
+
+def test_batch_few_heavy_jobs_and_many_light(oracle_c):
+    # heavy jobs (S_9 all transpositions) beside many light ones: the heavy
+    # ones leave the one-workgroup engine; every result stays exact
+    heavy = [(9, I.all_transpositions(9)), (9, I.pancake(9))]
+    light = [(n, g) for n, g in [(6, I.coxeter(6)), (7, I.star(7)), (5, I.lrx(5))] * 5]
+    jobs = heavy + light
+    res = api.growth_batch(jobs, max_layers=512)
+    for (n, gens), r in zip(jobs, res):
+        assert r.sizes == oracle_c.growth(n, gens, max_layers=512)[0]
