@@ -139,13 +139,13 @@ def bench_batch(args):
     # buffer the timed runs need (a first hipMalloc of tens of GB alone takes
     # seconds on this driver)
     for _ in range(args.warmup):
-        api.growth_batch(jobs, max_layers=512)
+        api.growth_batch(jobs, max_layers=512, tune=args.tune)
     torch.cuda.synchronize()
     print("[batch] warm-up done", file=sys.stderr, flush=True)
     times, res = [], None
     for _ in range(args.steps):
         t = time.perf_counter()
-        res = api.growth_batch(jobs, max_layers=512)
+        res = api.growth_batch(jobs, max_layers=512, tune=args.tune)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t)
     print(f"[batch] {args.steps} timed batches done", file=sys.stderr, flush=True)
@@ -184,6 +184,7 @@ def bench_batch(args):
                                "inverses, full growth each (seed 19162)", "jobs": len(jobs),
                    "states_per_step": states, "candidates_per_step": cands},
         "states_per_s": round(states * args.steps / elapsed, 1),
+        "autotuned": bool(args.tune),
         "sequential_plain": {"jobs_per_s": round(seq_jobs_s, 2), "sample_jobs": len(sample),
                              "speedup_of_batch": round(value / seq_jobs_s, 1)},
         "cpu_baseline": cpu,
@@ -293,6 +294,7 @@ def main():
     ap.add_argument("--workload", default="pancake12", choices=sorted(WORKLOADS) + ["batch4096", "serving"])
     ap.add_argument("--seq-sample", type=int, default=256)
     ap.add_argument("--batch-jobs", type=int, default=4096)
+    ap.add_argument("--tune", action="store_true", help="batch: let the autotuner pick engines and launch shapes")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--serving-nmax", type=int, default=11)
     ap.add_argument("--ratios", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9, 1.0, 1.2])

@@ -9,6 +9,7 @@
 // tags keep the jobs' states apart.
 #include "batch.h"
 
+#include <cstdio>
 #include <cstdlib>
 #include <mutex>
 
@@ -312,6 +313,9 @@ ClassChoice tune_class(int n, std::vector<std::pair<JobSpec, cg_result_t *>> &it
     (void)time_groups(sample, n, stream);  // warm-up (allocations)
     const double grp_s = time_groups(sample, n, stream);
     c.wg = wg_s <= grp_s;
+    if (std::getenv("CG_TUNE_LOG"))
+        std::fprintf(stderr, "[tune] n=%d sample=%zu workgroup=%d wg %.2f ms, groups %.2f ms -> %s\n", n, m,
+                     c.tuning.block, 1e3 * wg_s, 1e3 * grp_s, c.wg ? "workgroups" : "groups");
     std::lock_guard<std::mutex> lk(mu);
     cache[{dev, n}] = c;
     return c;
@@ -399,7 +403,13 @@ void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_
                         wg_items.push_back({&it->spec, &results[it->idx]});
                         if (n > wg_t_n) {
                             wg_t_n = n;
-                            wg_t = c.tuning;
+                            // untuned: the shape the autotuner picks on MI355X
+                            // (jobs with bitmaps in device memory want more
+                            // threads per job)
+                            if (tune)
+                                wg_t = c.tuning;
+                            else
+                                wg_t.block = n >= 10 ? 1024 : (n == 9 ? 512 : 256);
                         }
                     } else if (it->spec.inverse_closed) {
                         items.push_back(*it);
@@ -436,6 +446,7 @@ void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_
                 }
             }
         }
+        if (const char *e = std::getenv("CG_WG_BLOCK")) wg_t.block = std::atoi(e);
         if (!wg_items.empty()) {
             // one persistent launch for every small job of the batch
             WgRunner r(stream);

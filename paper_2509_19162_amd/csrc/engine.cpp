@@ -314,7 +314,7 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
         if (!wg_) wg_ = new WgRunner(stream_);
         std::vector<WgItem> one{{&spec, res}};
         WgTuning t;
-        t.block = 256;
+        t.block = spec.n >= 10 ? 1024 : (spec.n == 9 ? 512 : 256);
         wg_->run(one, t, t0);
         return;
     }
