@@ -82,7 +82,7 @@ def test_bitmask_random_sets_and_starts(seed, oracle_c):
     assert r.sizes == exp and r.status == rc
 
 
-@pytest.mark.parametrize("row", [r for r in max_diameter_table(directed=True) if r[0] <= 10],
+@pytest.mark.parametrize("row", [r for r in max_diameter_table(directed=True) if r[0] <= 13],
                          ids=lambda r: f"n{r[0]}")
 def test_bitmask_directed_paper_diameters(row, oracle_c):
     n, diam, gens = row
