@@ -272,6 +272,19 @@ void cg_queue_destroy(cg_queue_t *q);
  */
 void cg_release_cached_memory(void);
 
+/*
+ * Hands the library device memory to carve its buffers from (for example a
+ * tensor the caller allocated with PyTorch), on the current device:
+ * dev_ptr..dev_ptr+bytes becomes the arena; requests it cannot hold fall
+ * back to hipMalloc. The memory stays the caller's: the library never
+ * frees it, and the caller must keep it alive until the workspace is
+ * replaced. dev_ptr = NULL returns to an arena the library reserves itself.
+ * Returns CG_OK, CG_E_BUSY while buffers of engines, queues or batches still
+ * live in the current arena (destroy them first), or CG_E_INVAL (bytes too
+ * small, under 64 KiB).
+ */
+int cg_set_workspace(void *dev_ptr, size_t bytes);
+
 /* ---- growth statistics (host) -------------------------------------------- */
 /*
  * The growth read as a distribution of the distance d from the start over

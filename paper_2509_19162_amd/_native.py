@@ -135,6 +135,7 @@ SIGNATURES = [
     ("cg_queue_cancel", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     ("cg_queue_destroy", None, [ctypes.c_void_p]),
     ("cg_release_cached_memory", None, []),
+    ("cg_set_workspace", ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t]),
     ("cg_growth_stats", ctypes.c_int, [u64p, ctypes.c_int, ctypes.POINTER(CgGrowthStats)]),
     ("cg_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("cg_last_error", ctypes.c_char_p, []),

@@ -226,6 +226,26 @@ def growth_batch(jobs, max_layers: int = 256, max_active: int = 0, budget_bytes:
     return out
 
 
+_WORKSPACE = None  # keeps the caller's tensor alive while the library uses it
+
+
+def set_workspace(tensor) -> None:
+    """Let the library carve its device buffers out of ``tensor`` (a CUDA
+    tensor, e.g. ``torch.empty(nbytes, dtype=torch.uint8, device="cuda")``)
+    (``cg_set_workspace``); ``None`` returns to library-reserved memory.
+    Close engines and queues first (their buffers live in the old arena)."""
+    global _WORKSPACE
+    if tensor is None:
+        _check(N.lib().cg_set_workspace(None, 0))
+        _WORKSPACE = None
+        return
+    if not tensor.is_cuda or not tensor.is_contiguous():
+        raise ValueError("workspace must be a contiguous device tensor")
+    nbytes = tensor.numel() * tensor.element_size()
+    _check(N.lib().cg_set_workspace(ctypes.c_void_p(tensor.data_ptr()), nbytes))
+    _WORKSPACE = tensor
+
+
 def growth_stats(sizes: Sequence[int]) -> Dict[str, float]:
     """Statistics of a growth vector (``cg_growth_stats``): mean, mode,
     variance, skewness, excess kurtosis, moment-matched Gaussian and Gumbel

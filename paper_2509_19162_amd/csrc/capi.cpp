@@ -94,6 +94,13 @@ int cg_growth(int n, const uint8_t *gens, int n_gens, int max_layers, uint64_t *
     return cg_growth_ex(&job, &res, nullptr);
 }
 
+int cg_set_workspace(void *dev_ptr, size_t bytes) {
+    return guarded([&]() -> int {
+        cg::set_workspace(dev_ptr, bytes);
+        return CG_OK;
+    });
+}
+
 int cg_growth_stats(const uint64_t *sizes, int num_layers, cg_growth_stats_t *out) {
     return guarded([&]() -> int {
         if (!sizes || !out || num_layers < 1) throw cg::Error(CG_E_INVAL, "NULL sizes or result, or no layers");

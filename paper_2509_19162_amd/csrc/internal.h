@@ -117,6 +117,10 @@ struct DevBuf {
 // Returns the device arena to the driver when no buffer uses it
 // (cg_release_cached_memory).
 void release_cached_device_memory();
+// Makes [p, p + bytes) the current device's arena (p == nullptr: back to an
+// arena the library reserves itself). Throws CG_E_BUSY while buffers live
+// in the current arena.
+void set_workspace(void *p, size_t bytes);
 // Statistics of a growth vector (stats.cpp); throws Error(CG_E_INVAL).
 void growth_stats(const uint64_t *sizes, int num_layers, cg_growth_stats_t *out);
 

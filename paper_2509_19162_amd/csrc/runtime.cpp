@@ -39,6 +39,7 @@ struct Arena {
     char *base = nullptr;
     size_t size = 0;
     bool tried = false;
+    bool external = false;  // the caller's memory (cg_set_workspace): never freed here
     std::map<size_t, size_t> by_off;            // free ranges: offset -> length
     std::multimap<size_t, size_t> by_len;       // free ranges: length -> offset
     size_t used = 0;
@@ -149,10 +150,29 @@ void release_cached_device_memory() {
     std::lock_guard<std::mutex> lk(arenas().mu);
     for (auto &kv : arenas().arena) {
         Arena &A = kv.second;
-        if (!A.base || A.used) continue;  // ranges still handed out
+        if (!A.base || A.used || A.external) continue;  // in use, or the caller's
         (void)hipFree(A.base);
         A = Arena{};
     }
+}
+
+void set_workspace(void *p, size_t bytes) {
+    const int dev = current_device();
+    std::lock_guard<std::mutex> lk(arenas().mu);
+    Arena &A = arenas().arena[dev];
+    if (A.base && A.used) throw Error(CG_E_BUSY, "device buffers still live in the current workspace");
+    if (A.base && !A.external) (void)hipFree(A.base);
+    A = Arena{};
+    if (!p) return;  // back to memory the library reserves itself
+    const uintptr_t lo = ((uintptr_t)p + 255) & ~(uintptr_t)255;
+    const size_t skip = (size_t)(lo - (uintptr_t)p);
+    if (bytes <= skip + kAlign) throw Error(CG_E_INVAL, "workspace smaller than 64 KiB");
+    const size_t size = (bytes - skip) / kAlign * kAlign;
+    A.base = (char *)lo;
+    A.size = size;
+    A.external = true;
+    A.tried = true;
+    A.insert_free(0, size);
 }
 
 bool arena_active() {
