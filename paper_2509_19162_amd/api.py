@@ -291,8 +291,9 @@ class GrowthQueue:
     def __exit__(self, *exc):
         self.close()
 
-    def submit(self, n: int, gens, max_layers: int = 256, max_frontier: Optional[int] = None) -> int:
-        h = _JobHolder(n, gens, max_layers, max_frontier, 0, None, 0)
+    def submit(self, n: int, gens, max_layers: int = 256, max_frontier: Optional[int] = None,
+               start=None, allow_directed: bool = False) -> int:
+        h = _JobHolder(n, gens, max_layers, max_frontier, N.CG_ALLOW_DIRECTED if allow_directed else 0, start, 0)
         t = ctypes.c_uint64(0)
         _check(N.lib().cg_queue_submit(self._q, ctypes.byref(h.job), ctypes.byref(h.res), ctypes.byref(t)))
         self._jobs[int(t.value)] = h

@@ -368,6 +368,7 @@ void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_
     const double heavy = std::max((double)(1ull << 22), wg_total / 64.0);
     try {
         std::vector<WgItem> wg_items;
+        std::vector<Item *> alone;
         WgTuning wg_t;
         int wg_t_n = -1;
         for (auto &kv : by_n) {
@@ -380,11 +381,9 @@ void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_
             for (auto &it : all) {
                 if (wg_eligible(it.spec) && (!it.spec.inverse_closed || (double)work(it.spec) <= heavy))
                     wg_ok.push_back(&it);
-                else if (!it.spec.inverse_closed) {
-                    cg_result_t *r = &results[it.idx];
-                    r->status = CG_E_UNSUPPORTED;
-                    r->num_layers = 0;
-                } else
+                else if (!it.spec.inverse_closed)
+                    alone.push_back(&it);  // groups subtract two layers only
+                else
                     items.push_back(it);
             }
             if (!wg_ok.empty()) {
@@ -443,6 +442,20 @@ void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_
                     CG_HIP(hipStreamSynchronize(stream));
                     todo.push_back({span.first + (size_t)m / 2, (size_t)(m - m / 2)});
                     todo.push_back({span.first, (size_t)m / 2});
+                }
+            }
+        }
+        if (!alone.empty()) {
+            // directed jobs the small-job engine cannot take: one engine,
+            // one job after the other (every visited state subtracted)
+            Engine eng(stream);
+            for (Item *it : alone) {
+                cg_result_t *r = &results[it->idx];
+                try {
+                    eng.run(it->spec, r);
+                } catch (const Error &e) {
+                    r->status = e.code;
+                    r->num_layers = 0;
                 }
             }
         }

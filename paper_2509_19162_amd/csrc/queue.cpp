@@ -315,8 +315,10 @@ int cg_queue_submit(cg_queue_t *q, const cg_job_t *job, cg_result_t *res_slot, u
     const bool small = r->spec.n <= cg::kWgMaxN && cg::wg_eligible(r->spec) &&
                        states * (uint64_t)std::max(1, r->spec.k) <= cg::kSmallLaneWork;
     if (small) r->bytes = 3 * ((states + 31) / 32) * 4;  // the job's three bitmaps
-    r->big = !small &&
-             (r->spec.n > cg::kSharedN || r->spec.orbit_bound > cg::kLargeOrbit || r->bytes > q->budget / 4);
+    // the shared group subtracts layers d and d-1 only: directed jobs that
+    // are not small take a lane (its engine subtracts every visited state)
+    r->big = !small && (!r->spec.inverse_closed || r->spec.n > cg::kSharedN ||
+                        r->spec.orbit_bound > cg::kLargeOrbit || r->bytes > q->budget / 4);
     // large permutation jobs from n = 12 run in the bitmask engine: 3 bits
     // per state of S_n instead of 8-byte layers and candidate arrays (an
     // S_13 job holds 2.3 GB there); results are the same

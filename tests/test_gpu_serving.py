@@ -1,6 +1,7 @@
 """Serving queue (cg_queue_*): continuous batching must not change any
 result: each job's growth in the mix equals its growth alone (tolerance 0)."""
 
+import math
 import threading
 
 import pytest
@@ -102,3 +103,31 @@ def test_queue_serves_s13_requests_beside_small_ones(oracle_c):
         assert sum(r12.sizes) == 479001600 and len(r12.sizes) == 15
         r13 = q.wait(t13, timeout_s=300)
         assert r13.sizes == mahonian(13)
+
+
+def test_queue_directed_and_coset_requests(oracle_c):
+    # directed sets: small ones in the small-job lane, larger ones on a lane
+    # whose engine subtracts every visited state; a coset start in the group
+    jobs = [(7, I.lx(7), None), (11, I.lx(11), None), (9, I.lx(9), None)]
+    start = I.binary_central_state(12)
+    with api.GrowthQueue(max_active=16) as q:
+        ts = [q.submit(n, g, max_layers=512, allow_directed=True) for n, g, _ in jobs]
+        tc = q.submit(12, I.all_transpositions(12), max_layers=64, start=start)
+        for (n, g, _), t in zip(jobs, ts):
+            r = q.wait(t, timeout_s=120)
+            if n <= 9:
+                assert r.sizes == oracle_c.growth(n, g, max_layers=512)[0]
+            else:
+                assert sum(r.sizes) == math.factorial(n)
+                assert len(r.sizes) - 1 == (3 * n * n - 8 * n + 9) // 4
+        r = q.wait(tc, timeout_s=120)
+        assert r.sizes == oracle_c.growth(12, I.all_transpositions(12), max_layers=64, start=start)[0]
+
+
+def test_batch_directed_heavy_job_runs_alone(oracle_c):
+    jobs = [(10, I.lx(10)), (7, I.lx(7)), (6, I.coxeter(6))]
+    res = api.growth_batch(jobs, max_layers=512, allow_directed=True)
+    assert res[0].status == N.CG_OK and sum(res[0].sizes) == math.factorial(10)
+    assert len(res[0].sizes) - 1 == (3 * 100 - 80 + 12) // 4
+    for (n, g), r in list(zip(jobs, res))[1:]:
+        assert r.sizes == oracle_c.growth(n, g, max_layers=512)[0]
