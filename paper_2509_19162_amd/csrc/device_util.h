@@ -89,7 +89,11 @@ constexpr uint32_t kSpinLimit = 1u << 24;
 #ifndef CG_LB_DEPTH
 #define CG_LB_DEPTH 4
 #endif
-constexpr int kLbDepth = CG_LB_DEPTH;  // predecessor words read per look-back round
+constexpr int kLbDepth = CG_LB_DEPTH;  // predecessor words read in the first look-back round
+#ifndef CG_LB_DEPTH_FAR
+#define CG_LB_DEPTH_FAR 8
+#endif
+constexpr int kLbDepthFar = CG_LB_DEPTH_FAR;  // ... and in every later round
 
 __device__ __forceinline__ uint64_t lb_word(uint32_t epoch, uint32_t flag, uint64_t v) {
     return ((uint64_t)epoch << 48) | ((uint64_t)flag << 46) | (v & kValueMask);
@@ -104,34 +108,47 @@ __device__ __forceinline__ uint64_t lb_load(const uint64_t *p) {
                              __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// One look-back round: reads the words of tiles t, t-1, ..., t-D+1 at once
+// and adds the aggregates up to the first inclusive word, stopping at a
+// word not yet published. Returns the tiles consumed; *done is set when an
+// inclusive word was reached.
+template <int D>
+__device__ __forceinline__ int lb_round(const uint64_t *base, uint64_t stride, int64_t t, uint32_t epoch,
+                                        uint64_t &excl, bool &done) {
+    const uint64_t zero_incl = lb_word(epoch, kFlagInclusive, 0);
+    uint64_t w[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) w[u] = (t - u >= 0) ? lb_load(base + (uint64_t)(t - u) * stride) : zero_incl;
+    int used = 0;
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+        if (done || used != u) break;
+        if ((uint32_t)(w[u] >> 48) != epoch) break;
+        excl += w[u] & kValueMask;
+        ++used;
+        if (((w[u] >> 46) & 3u) == kFlagInclusive) done = true;
+    }
+    return used;
+}
+
 // Exclusive prefix of tile `tile` from the words of tiles tile-1, tile-2, ...
-// located at base[t * stride]; kLbDepth predecessors are read per round so
-// a chain of aggregates costs fewer round trips. Tiles publish in
-// ticket order, so every tile waited on is already running; the wait is
-// still bounded: on overrun the error flag is raised and the (then
-// meaningless) partial sum returned.
+// located at base[t * stride]. The first round reads kLbDepth predecessors
+// (enough when a nearby tile has already published its inclusive word);
+// later rounds read kLbDepthFar, so a long chain of aggregates costs few
+// round trips. Tiles publish in ticket order, so every tile waited on is
+// already running; the wait is still bounded: on overrun the error flag is
+// raised and the (then meaningless) partial sum returned.
 __device__ __forceinline__ uint64_t lb_lookback(const uint64_t *base, uint64_t stride,
                                                 uint32_t tile, uint32_t epoch,
                                                 uint32_t *err) {
     uint64_t excl = 0;
     int64_t t = (int64_t)tile - 1;
     uint32_t spins = 0;
-    const uint64_t zero_incl = lb_word(epoch, kFlagInclusive, 0);
+    bool first = true;
     while (t >= 0) {
-        uint64_t w[kLbDepth];
-#pragma unroll
-        for (int u = 0; u < kLbDepth; ++u)
-            w[u] = (t - u >= 0) ? lb_load(base + (uint64_t)(t - u) * stride) : zero_incl;
-        int used = 0;
         bool done = false;
-#pragma unroll
-        for (int u = 0; u < kLbDepth; ++u) {
-            if (done || used != u) break;
-            if ((uint32_t)(w[u] >> 48) != epoch) break;
-            excl += w[u] & kValueMask;
-            ++used;
-            if (((w[u] >> 46) & 3u) == kFlagInclusive) done = true;
-        }
+        const int used = first ? lb_round<kLbDepth>(base, stride, t, epoch, excl, done)
+                               : lb_round<kLbDepthFar>(base, stride, t, epoch, excl, done);
         if (done) break;
         t -= used;
         if (used == 0) {
@@ -140,6 +157,8 @@ __device__ __forceinline__ uint64_t lb_lookback(const uint64_t *base, uint64_t s
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
+        } else {
+            first = false;
         }
     }
     return excl;
