@@ -53,16 +53,25 @@ __host__ __device__ __forceinline__ uint64_t perm_unrank(uint32_t rank, int n) {
 // the rank type: uint32_t up to n = 12, uint64_t beyond (16! < 2^45).
 template <int N, class R = uint32_t>
 __host__ __device__ __forceinline__ R perm_rank_t(uint64_t key) {
-    R rank = 0;
-    uint32_t used = 0;
+    // c_i = number of values below s[i] not used before position i: the
+    // popcount of the low s[i] bits of the still-unused set. The first
+    // position has c_0 = s[0]; the last always has c = 0.
+    if constexpr (N <= 1) {
+        return 0;
+    } else {
+        uint32_t unused = (1u << N) - 1u;
+        const uint32_t v0 = (uint32_t)(key >> (4 * (N - 1))) & 15u;
+        R rank = (R)v0;
+        unused ^= 1u << v0;
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-        const uint32_t v = (uint32_t)(key >> (4 * (N - 1 - i))) & 15u;
-        const uint32_t c = v - (uint32_t)__builtin_popcount(used & ((1u << v) - 1u));
-        rank = rank * (R)(N - i) + (R)c;
-        used |= 1u << v;
+        for (int i = 1; i < N - 1; ++i) {
+            const uint32_t v = (uint32_t)(key >> (4 * (N - 1 - i))) & 15u;
+            const uint32_t c = (uint32_t)__builtin_popcount(unused & ((1u << v) - 1u));
+            rank = rank * (R)(N - i) + (R)c;
+            unused ^= 1u << v;
+        }
+        return rank;  // the last position's digit is 0 (radix 1)
     }
-    return rank;
 }
 
 template <int N, class R = uint32_t>
