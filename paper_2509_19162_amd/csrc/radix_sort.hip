@@ -55,6 +55,9 @@ struct TileOf {
     static constexpr int wave_seg = kWave * ipt;  // keys owned by one wave
 };
 constexpr int kTile = TileOf<uint64_t>::tile;  // the shortest tile: sizes look-back state
+#ifndef CG_EXPAND_CONTIG
+#define CG_EXPAND_CONTIG 1  // ranked-expand threads take consecutive frontier states
+#endif
 #ifndef CG_SORT_ROWS
 #define CG_SORT_ROWS 1
 #endif
@@ -188,9 +191,6 @@ __global__ __launch_bounds__(kBlock) void hist_kernel(Src src, uint32_t ntiles, 
 #define CG_EXPAND_IPT 4
 #endif
 constexpr int kExpandIpt = CG_EXPAND_IPT;  // frontier states per thread and round
-#ifndef CG_EXPAND_CONTIG
-#define CG_EXPAND_CONTIG 1
-#endif
 // Frontier state j of the calling thread within a round of kBlock*kExpandIpt
 // states: consecutive per thread (CG_EXPAND_CONTIG, the default) or strided
 // across the block. Consecutive states of the sorted frontier share their
