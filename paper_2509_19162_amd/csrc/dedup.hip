@@ -37,8 +37,11 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kIpt = 16;
-constexpr int kTile = kBlock * kIpt;  // 4096
+#ifndef CG_DEDUP_IPT
+#define CG_DEDUP_IPT 16
+#endif
+constexpr int kIpt = CG_DEDUP_IPT;
+constexpr int kTile = kBlock * kIpt;  // 4096 candidates per dedup tile by default
 // largest candidate array looked up from the reference side (4 MB of u32)
 constexpr uint64_t kMarkMaxCandidates = 1u << 20;
 
