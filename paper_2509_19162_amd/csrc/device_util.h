@@ -87,11 +87,11 @@ constexpr uint32_t kFlagInclusive = 2;
 constexpr uint64_t kValueMask = (1ull << 46) - 1;
 constexpr uint32_t kSpinLimit = 1u << 24;
 #ifndef CG_LB_DEPTH
-#define CG_LB_DEPTH 4
+#define CG_LB_DEPTH 1
 #endif
 constexpr int kLbDepth = CG_LB_DEPTH;  // predecessor words read in the first look-back round
 #ifndef CG_LB_DEPTH_FAR
-#define CG_LB_DEPTH_FAR 8
+#define CG_LB_DEPTH_FAR 4
 #endif
 constexpr int kLbDepthFar = CG_LB_DEPTH_FAR;  // ... and in every later round
 

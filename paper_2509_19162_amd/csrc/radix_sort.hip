@@ -37,14 +37,24 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-// Keys per thread: 16 for 64-bit keys (256 threads, 4096-key tiles), 32 for
-// 32-bit keys (512 threads, 16384-key tiles). Longer tiles mean fewer tiles
-// chained through the look-back for the same keys in flight.
+// Keys per thread: 16 for 64-bit keys (256 threads, 4096-key tiles), 30 for
+// 32-bit keys (512 threads, 15360-key tiles). A pass is bound by the keys in
+// flight over a tile's latency (most of it the look-back): 30 keys, their
+// packed ranks and the look-back fit 80 VGPRs, which with the split LDS
+// reorder below keeps 3 tiles resident per CU (32 keys need 88 VGPRs: 2).
 #ifndef CG_SORT_IPT32
-#define CG_SORT_IPT32 32
+#define CG_SORT_IPT32 30
 #endif
 #ifndef CG_SORT_BLOCK32
 #define CG_SORT_BLOCK32 512
+#endif
+// The LDS reorder of a sort tile runs in `split` rounds over a buffer of
+// tile/split keys: less LDS per tile, more tiles resident per CU.
+#ifndef CG_SORT_SPLIT32
+#define CG_SORT_SPLIT32 2
+#endif
+#ifndef CG_SORT_SPLIT64
+#define CG_SORT_SPLIT64 2
 #endif
 template <class K>
 struct TileOf {
@@ -53,6 +63,8 @@ struct TileOf {
     static constexpr int waves = block / kWave;
     static constexpr int tile = block * ipt;
     static constexpr int wave_seg = kWave * ipt;  // keys owned by one wave
+    static constexpr int split = sizeof(K) == 4 ? CG_SORT_SPLIT32 : CG_SORT_SPLIT64;
+    static constexpr int buf = tile / split;  // keys in the LDS reorder buffer
 };
 constexpr int kTile = TileOf<uint64_t>::tile;  // the shortest tile: sizes look-back state
 #ifndef CG_EXPAND_CONTIG
@@ -288,11 +300,11 @@ __global__ void clear_kernel(unsigned long long *__restrict__ a, uint32_t na,
 }
 
 // ---- 3. one scatter pass -----------------------------------------------------------------
-#ifdef CG_SORT_WPE
-#define CG_SORT_ATTR __attribute__((amdgpu_waves_per_eu(CG_SORT_WPE)))
-#else
-#define CG_SORT_ATTR
+// 6 waves per SIMD: at most 80 VGPRs (the register budget above)
+#ifndef CG_SORT_WPE
+#define CG_SORT_WPE 6
 #endif
+#define CG_SORT_ATTR __attribute__((amdgpu_waves_per_eu(CG_SORT_WPE)))
 // Lookback = true: tiles take tickets and chain their digit offsets by
 // decoupled look-back. Lookback = false: tile = block index and each
 // tile's digit offsets come precomputed in tile_off (reduce-then-scan).
@@ -308,8 +320,11 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
     constexpr int kWaveSeg = TileOf<K>::wave_seg;
     constexpr int kBlk = TileOf<K>::block;
     constexpr int kWv = TileOf<K>::waves;
+    constexpr int kSplit = TileOf<K>::split;
+    constexpr int kBuf = TileOf<K>::buf;
     static_assert(kBlk >= kRadix, "one thread per digit in the look-back");
-    __shared__ __align__(16) K s_keys[kTileK];
+    static_assert(kIpt % 2 == 0 && kBuf * kSplit == kTileK, "two halves per register, whole rounds");
+    __shared__ __align__(16) K s_keys[kBuf];
     __shared__ uint32_t s_cnt[kWv][kRadix];
     __shared__ uint64_t s_gstart[kRadix];
     __shared__ uint32_t s_lstart[kRadix];
@@ -318,8 +333,8 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
 
     // the digit masks of the ranking live in s_keys until the scatter
     uint64_t(*s_match)[kWv][kRadix] = reinterpret_cast<uint64_t(*)[kWv][kRadix]>(s_keys);
-    static_assert(kRows * kWv * kRadix * sizeof(uint64_t) <= kTileK * sizeof(K),
-                  "match words fit in the key tile");
+    static_assert(kRows * kWv * kRadix * sizeof(uint64_t) <= kBuf * sizeof(K),
+                  "match words fit in the reorder buffer");
     static_assert(kIpt % kRows == 0, "rows per group divide the rows per thread");
 
     const uint32_t tid = threadIdx.x;
@@ -356,8 +371,10 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
     // digit's first holder, the group's count. LDS instructions of one wave
     // are processed in issue order, so every read sees all ORs of its group
     // and no clear overtakes a read.
-    uint32_t rank[kIpt];  // (rank within the wave's digit run) | digit << 16
-    static_assert(kTileK <= (1 << 16), "ranks fit in 16 bits");
+    // Item j's rank within the wave's digit run (< 2^16) sits in half j & 1
+    // of rank2[j / 2]; the digit is taken from the key again when needed.
+    uint32_t rank2[kIpt / 2];
+    static_assert(kTileK <= (1 << 16), "ranks and tile positions fit in 16 bits");
 #pragma unroll
     for (int j0 = 0; j0 < kIpt; j0 += kRows) {
         uint32_t d[kRows];
@@ -393,11 +410,14 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
                     first = first && c == 0;
                 }
             }
-            rank[j0 + r] = (old[r] + before) | (d[r] << 16);  // rank < 2^16 beside the digit
-            // materialise the packed rank here: left to itself the compiler
-            // keeps digit, count and lane rank of every row apart until the
-            // scatter, which costs two extra registers per row
-            __asm__ volatile("" : "+v"(rank[j0 + r]));
+            const int j = j0 + r;
+            if (j & 1)
+                rank2[j >> 1] |= (old[r] + before) << 16;
+            else
+                rank2[j >> 1] = old[r] + before;
+            // materialise the rank here: left to itself the compiler keeps
+            // count and lane rank of every row apart until the scatter
+            __asm__ volatile("" : "+v"(rank2[j >> 1]));
             if (first) s_cnt[wave][d[r]] = old[r] + total;
         }
     }
@@ -442,21 +462,43 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
     }
     __syncthreads();
 
+    // rank within the wave's run -> position in the tile-sorted order
 #pragma unroll
-    for (int j = 0; j < kIpt; ++j) {
-        const uint32_t d = rank[j] >> 16;
-        s_keys[s_cnt[wave][d] + (rank[j] & 0xFFFFu)] = key[j];
+    for (int j = 0; j < kIpt; j += 2) {
+        // digits taken afresh (opaque copies of the keys): reusing the ones
+        // of the ranking would keep 32 of them live across the look-back
+        K k0 = key[j], k1 = key[j + 1];
+        __asm__ volatile("" : "+v"(k0), "+v"(k1));
+        const uint32_t d0 = (uint32_t)(k0 >> shift) & dmask;
+        const uint32_t d1 = (uint32_t)(k1 >> shift) & dmask;
+        const uint32_t p0 = s_cnt[wave][d0] + (rank2[j >> 1] & 0xFFFFu);
+        const uint32_t p1 = s_cnt[wave][d1] + (rank2[j >> 1] >> 16);
+        rank2[j >> 1] = p0 | (p1 << 16);
     }
-    __syncthreads();
-
-    for (uint32_t i = tid; i < nvalid; i += kBlk) {
-        const K k = s_keys[i];
-        const uint32_t d = (uint32_t)(k >> shift) & dmask;
-        const uint64_t gpos = s_gstart[d] + (i - s_lstart[d]);
-        if (gpos < total)
-            out[gpos] = k;
-        else
-            atomicOr(err, 2u);  // inconsistent offsets: never write out of bounds
+    // Reorder through LDS in rounds of kBuf positions, so that each digit's
+    // run goes out as one contiguous write. Positions at or past nvalid hold
+    // padding keys.
+#pragma unroll
+    for (int h = 0; h < kSplit; ++h) {
+        const uint32_t lo = (uint32_t)h * kBuf;
+        if (lo >= nvalid) break;  // same for the whole block
+        if (h) __syncthreads();   // the previous round's readers are done
+#pragma unroll
+        for (int j = 0; j < kIpt; ++j) {
+            const uint32_t p = ((j & 1) ? rank2[j >> 1] >> 16 : rank2[j >> 1] & 0xFFFFu) - lo;
+            if (p < (uint32_t)kBuf) s_keys[p] = key[j];
+        }
+        __syncthreads();
+        const uint32_t cnt = nvalid - lo < (uint32_t)kBuf ? nvalid - lo : (uint32_t)kBuf;
+        for (uint32_t i = tid; i < cnt; i += kBlk) {
+            const K k = s_keys[i];
+            const uint32_t d = (uint32_t)(k >> shift) & dmask;
+            const uint64_t gpos = s_gstart[d] + (lo + i - s_lstart[d]);
+            if (gpos < total)
+                out[gpos] = k;
+            else
+                atomicOr(err, 2u);  // inconsistent offsets: never write out of bounds
+        }
     }
 }
 
