@@ -42,6 +42,7 @@ constexpr int kWaves = kBlock / kWave;
 #endif
 constexpr int kIpt = CG_DEDUP_IPT;
 constexpr int kTile = kBlock * kIpt;  // 4096 candidates per dedup tile by default
+constexpr int kRefIpt = 4;            // reference keys per thread loaded with the tile
 // largest candidate array looked up from the reference side (4 MB of u32)
 constexpr uint64_t kMarkMaxCandidates = 1u << 20;
 
@@ -148,18 +149,11 @@ __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
     const uint64_t left = C - base;
     const uint32_t nvalid = (uint32_t)(left < (uint64_t)kTile ? left : (uint64_t)kTile);
 
-#pragma unroll
-    for (int j = 0; j < kIpt; ++j) {
-        const uint32_t i = j * kBlock + tid;
-        s_keys[pad(i)] = i < nvalid ? S[base + i] : (K)kSentinel;
-        s_kill[i] = (gkill && i < nvalid) ? gkill[base + i] : 0;
-    }
-    const bool has_prev = base > 0;
-    const K prev_global = has_prev ? S[base - 1] : (K)0;
+    // The slices of the reference layers come first: the loads of the first
+    // kRefIpt references per thread then go out together with the tile's
+    // candidates instead of one latency after another.
     uint64_t bnd[4] = {0, 0, 0, 0};
-    if (gkill) {
-        na = nb = 0;  // matches already flagged by mark_refs_kernel
-    }
+    if (gkill) na = nb = 0;  // matches already flagged by mark_refs_kernel
     if (na) {
         bnd[0] = bounds[4 * (uint64_t)tile];
         bnd[1] = bounds[4 * (uint64_t)tile + 1];
@@ -168,26 +162,51 @@ __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
         bnd[2] = bounds[4 * (uint64_t)tile + 2];
         bnd[3] = bounds[4 * (uint64_t)tile + 3];
     }
+    K kin[kIpt];
+#pragma unroll
+    for (int j = 0; j < kIpt; ++j) {
+        const uint32_t i = j * kBlock + tid;
+        kin[j] = i < nvalid ? S[base + i] : (K)kSentinel;
+    }
+    const bool has_prev = base > 0;
+    const K prev_global = has_prev ? S[base - 1] : (K)0;
+    // references of both slices as one list: A's slice, then B's
+    const uint64_t n_a = bnd[1] - bnd[0];
+    const uint64_t n_ref = n_a + (bnd[3] - bnd[2]);
+    auto ref_at = [&](uint64_t t) -> K {
+        return pol.from_layer(t < n_a ? A[bnd[0] + t] : B[bnd[2] + (t - n_a)]);
+    };
+    K ref[kRefIpt];
+#pragma unroll
+    for (int u = 0; u < kRefIpt; ++u) {
+        const uint64_t t = (uint64_t)u * kBlock + tid;
+        ref[u] = t < n_ref ? ref_at(t) : (K)0;
+    }
+#pragma unroll
+    for (int j = 0; j < kIpt; ++j) {
+        const uint32_t i = j * kBlock + tid;
+        s_keys[pad(i)] = kin[j];
+        s_kill[i] = (gkill && i < nvalid) ? gkill[base + i] : 0;
+    }
     __syncthreads();
 
     // Reference keys in the tile's range are far fewer than candidates: each
     // one looks itself up in the sorted tile (12 LDS probes) and marks the
     // first equal candidate; later copies of a key are dropped as repeats.
-    for (int r = 0; r < 2; ++r) {
-        const typename P::Ref *R = r == 0 ? A : B;
-        const uint64_t lo = bnd[2 * r], hi = bnd[2 * r + 1];
-        for (uint64_t i = lo + tid; i < hi; i += kBlock) {
-            const K key = pol.from_layer(R[i]);
-            uint32_t pos = 0, len = nvalid;
-            while (len > 1) {
-                const uint32_t half = len >> 1;
-                pos = s_keys[pad(pos + half)] < key ? pos + half : pos;
-                len -= half;
-            }
-            const uint32_t lb = pos + (s_keys[pad(pos)] < key ? 1u : 0u);
-            if (lb < nvalid && s_keys[pad(lb)] == key) s_kill[lb] = 1;
+    auto mark = [&](K key) {
+        uint32_t pos = 0, len = nvalid;
+        while (len > 1) {
+            const uint32_t half = len >> 1;
+            pos = s_keys[pad(pos + half)] < key ? pos + half : pos;
+            len -= half;
         }
-    }
+        const uint32_t lb = pos + (s_keys[pad(pos)] < key ? 1u : 0u);
+        if (lb < nvalid && s_keys[pad(lb)] == key) s_kill[lb] = 1;
+    };
+#pragma unroll
+    for (int u = 0; u < kRefIpt; ++u)
+        if ((uint64_t)u * kBlock + tid < n_ref) mark(ref[u]);
+    for (uint64_t t = (uint64_t)kRefIpt * kBlock + tid; t < n_ref; t += kBlock) mark(ref_at(t));
     __syncthreads();
 
     K k[kIpt];
