@@ -216,14 +216,40 @@ __device__ __forceinline__ uint32_t expand_slot(int j) {
     return (uint32_t)j * kBlock + threadIdx.x;
 #endif
 }
-#ifndef CG_HIST_RUNLEN
-#define CG_HIST_RUNLEN 1  // count runs of equal digits per thread before each LDS atomic
+// Digits of the low passes change from one candidate to the next: they go
+// to LDS counters one by one. Higher digits come in runs (a thread's
+// consecutive frontier states map to nearby ranks): each thread counts the
+// run of its current digit and adds it when the digit changes.
+#ifndef CG_HIST_DIRECT_PASSES
+#define CG_HIST_DIRECT_PASSES 1
 #endif
+
+// Bits of the ranks of S_N (the smallest b with 2^b >= N!) and the sort
+// passes over them, fixed at compile time for the ranked expand.
+template <int N>
+struct RankPasses {
+    static constexpr uint64_t fact() {
+        uint64_t f = 1;
+        for (int i = 2; i <= N; ++i) f *= (uint64_t)i;
+        return f;
+    }
+    static constexpr int bits() {
+        int b = 0;
+        while ((1ull << b) < fact()) ++b;
+        return b;
+    }
+    static constexpr int passes = (bits() + kRadixBits - 1) / kRadixBits;
+    static constexpr uint32_t mask(int p) {
+        return (1u << ((bits() - p * kRadixBits) < kRadixBits ? (bits() - p * kRadixBits) : kRadixBits)) - 1u;
+    }
+};
 
 template <int N>
 __global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
     const uint64_t *__restrict__ frontier, uint64_t F, const GenSel *__restrict__ gsel, int k,
-    uint32_t *__restrict__ out, uint64_t per_block, PassDesc pd, unsigned long long *__restrict__ ghist) {
+    uint32_t *__restrict__ out, uint64_t per_block, unsigned long long *__restrict__ ghist) {
+    constexpr int kP = RankPasses<N>::passes;
+    static_assert(kP <= kMaxPasses, "rank passes");
     __shared__ uint32_t s_h[kMaxPasses][kRadix];
     for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kBlock) (&s_h[0][0])[i] = 0;
     __syncthreads();
@@ -252,30 +278,27 @@ __global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
                 const uint32_t r = perm_rank_t<N>(apply_gensel(st[j], sel));
                 o[f] = r;
 #pragma unroll
-                for (int p = 0; p < kMaxPasses; ++p) {
-                    if (p < pd.passes) {
-                        const uint32_t d = (r >> pd.shift[p]) & pd.mask[p];
-#if CG_HIST_RUNLEN
-                        if (d != cur[p]) {
-                            if (run[p]) atomicAdd(&s_h[p][cur[p]], run[p]);
-                            cur[p] = d;
-                            run[p] = 1;
-                        } else {
-                            ++run[p];
-                        }
-#else
+                for (int p = 0; p < kP; ++p) {
+                    const uint32_t d = (r >> (p * kRadixBits)) & RankPasses<N>::mask(p);
+                    if (p < CG_HIST_DIRECT_PASSES) {
                         atomicAdd(&s_h[p][d], 1u);
-#endif
+                    } else if (d != cur[p]) {
+                        if (run[p]) atomicAdd(&s_h[p][cur[p]], run[p]);
+                        cur[p] = d;
+                        run[p] = 1;
+                    } else {
+                        ++run[p];
                     }
                 }
             }
         }
     }
 #pragma unroll
-    for (int p = 0; p < kMaxPasses; ++p)
-        if (p < pd.passes && run[p]) atomicAdd(&s_h[p][cur[p]], run[p]);
+    for (int p = 0; p < kP; ++p)
+        if (p >= CG_HIST_DIRECT_PASSES && run[p]) atomicAdd(&s_h[p][cur[p]], run[p]);
     __syncthreads();
-    for (int p = 0; p < pd.passes; ++p) {
+#pragma unroll
+    for (int p = 0; p < kP; ++p) {
         const uint32_t c = s_h[p][threadIdx.x];
         if (c) atomicAdd(&ghist[p * kRadix + threadIdx.x], (unsigned long long)c);
     }
@@ -744,7 +767,6 @@ uint32_t *expand_rank_sort(int n, const uint64_t *frontier, uint64_t F, const Ge
     const uint64_t C = F * (uint64_t)k;
     if (C == 0) return buf0;
     w.ensure_status(sort_status_words(C));
-    const PassDesc pd = make_passes(0, rank_bits);
     unsigned long long *hist = w.hist.as<unsigned long long>();
     if (w.prof) w.prof->begin(K_AUX);
     hipLaunchKernelGGL(clear_kernel, dim3(8), dim3(256), 0, w.stream, hist, (uint32_t)(kMaxPasses * kRadix),
@@ -759,8 +781,11 @@ uint32_t *expand_rank_sort(int n, const uint64_t *frontier, uint64_t F, const Ge
     const uint32_t grid = (uint32_t)((F + per_block - 1) / per_block);
     if (w.prof) w.prof->begin(K_EXPAND);
     with_rank_n(n, [&](auto NN) {
-        hipLaunchKernelGGL(expand_rank_hist_kernel<decltype(NN)::value>, dim3(grid), dim3(kBlock), 0, w.stream,
-                           frontier, F, d_gsel, k, buf0, per_block, pd, hist);
+        constexpr int N = decltype(NN)::value;
+        // the kernel's histograms follow the bits of S_N's ranks
+        if (rank_bits != RankPasses<N>::bits()) throw Error(-1, "rank bits differ from those of n!");
+        hipLaunchKernelGGL(expand_rank_hist_kernel<N>, dim3(grid), dim3(kBlock), 0, w.stream, frontier, F,
+                           d_gsel, k, buf0, per_block, hist);
     });
     CG_HIP(hipGetLastError());
     if (w.prof) w.prof->end(K_EXPAND, 8.0 * (double)F + 4.0 * (double)C, (double)C);
