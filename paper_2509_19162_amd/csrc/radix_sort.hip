@@ -74,6 +74,9 @@ constexpr int kTile = TileOf<uint64_t>::tile;  // the shortest tile: sizes look-
 #define CG_SORT_ROWS 1
 #endif
 constexpr int kRows = CG_SORT_ROWS;  // rows ranked per LDS round trip
+#ifndef CG_SORT_HALF_MASK
+#define CG_SORT_HALF_MASK 1  // peer masks set and cleared by 32-bit halves
+#endif
 
 static_assert(kBlock == kRadix, "one thread per digit in the look-back");
 
@@ -403,8 +406,15 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
         uint32_t d[kRows];
 #pragma unroll
         for (int r = 0; r < kRows; ++r) d[r] = (uint32_t)(key[j0 + r] >> shift) & dmask;
+#if CG_SORT_HALF_MASK
+        // a lane sets (and later clears) only its half-wave's 32-bit word
+#pragma unroll
+        for (int r = 0; r < kRows; ++r)
+            atomicOr(reinterpret_cast<uint32_t *>(&s_match[r][wave][d[r]]) + (lane >> 5), 1u << (lane & 31));
+#else
 #pragma unroll
         for (int r = 0; r < kRows; ++r) atomicOr(&s_match[r][wave][d[r]], 1ull << lane);
+#endif
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         uint64_t m[kRows][kRows];
@@ -417,8 +427,13 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
+#if CG_SORT_HALF_MASK
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) reinterpret_cast<uint32_t *>(&s_match[r][wave][d[r]])[lane >> 5] = 0u;
+#else
 #pragma unroll
         for (int r = 0; r < kRows; ++r) s_match[r][wave][d[r]] = 0ull;
+#endif
 #pragma unroll
         for (int r = 0; r < kRows; ++r) {
             uint32_t before = mask_rank(m[r][r]);
