@@ -54,6 +54,14 @@ int cg_test_sort(uint64_t *d_keys, uint64_t *d_tmp, uint64_t count,
                  int bit_lo, int bit_hi, void *stream);
 
 /*
+ * The same for 32-bit keys (0 <= bit_lo < bit_hi <= 32): the sort the
+ * growth step runs on the lexicographic ranks of candidates for n <= 12,
+ * with its own tile shape. d_tmp holds count keys.
+ */
+int cg_test_sort32(uint32_t *d_keys, uint32_t *d_tmp, uint64_t count,
+                   int bit_lo, int bit_hi, void *stream);
+
+/*
  * Unique + set difference + compaction: from the sorted d_sorted[0..C)
  * keep each key once, and only if it is in neither sorted array d_a[0..na)
  * nor d_b[0..nb). The kept keys go to d_out in increasing order;

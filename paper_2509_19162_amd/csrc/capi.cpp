@@ -236,6 +236,25 @@ int cg_test_sort(uint64_t *d_keys, uint64_t *d_tmp, uint64_t count, int bit_lo, 
     });
 }
 
+int cg_test_sort32(uint32_t *d_keys, uint32_t *d_tmp, uint64_t count, int bit_lo, int bit_hi,
+                   void *stream) {
+    return guarded([&]() -> int {
+        if (bit_lo < 0 || bit_hi > 32 || bit_lo >= bit_hi) throw cg::Error(CG_E_INVAL, "bad bit range");
+        if (count && (!d_keys || !d_tmp)) throw cg::Error(CG_E_INVAL, "NULL device pointer");
+        hipStream_t s = (hipStream_t)stream;
+        cg::PipeWork w;
+        w.init(s);
+        uint32_t *res = cg::radix_sort32(d_keys, d_tmp, count, bit_lo, bit_hi, w);
+        if (res != d_keys)
+            CG_HIP(hipMemcpyAsync(d_keys, res, count * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        uint32_t err = 0;
+        CG_HIP(hipMemcpyAsync(&err, w.err(), sizeof err, hipMemcpyDeviceToHost, s));
+        CG_HIP(hipStreamSynchronize(s));
+        if (err) throw cg::Error(CG_E_DEVICE, "kernel error flag set (look-back bound or offset check)");
+        return CG_OK;
+    });
+}
+
 int cg_test_dedup(const uint64_t *d_sorted, uint64_t C, const uint64_t *d_a, uint64_t na,
                   const uint64_t *d_b, uint64_t nb, uint64_t *d_out, uint64_t *h_count,
                   void *stream) {

@@ -48,6 +48,35 @@ __host__ __device__ __forceinline__ uint64_t perm_unrank(uint32_t rank, int n) {
     return key;
 }
 
+// a * b + c for a, b < 2^24 (both factors of every use below are): a 24-bit
+// multiply-add for 32-bit ranks, a plain one for 64-bit ranks (the product
+// may exceed 32 bits there).
+template <class R>
+__host__ __device__ __forceinline__ R mad24(R a, R b, R c) {
+#ifdef __HIP_DEVICE_COMPILE__
+    if constexpr (sizeof(R) == 4) {
+        // written out: left to itself the compiler reassociates the Horner
+        // chain into 32-bit multiplies (quarter rate)
+        uint32_t r;
+        __asm__("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"((uint32_t)a), "s"((uint32_t)b), "v"((uint32_t)c));
+        return (R)r;
+    }
+#endif
+    return a * b + c;
+}
+
+// Last position whose Horner prefix N (N-1) ... (N-i) stays below 2^24.
+template <int N>
+constexpr int rank_split() {
+    uint64_t bound = (uint64_t)N;
+    int i = 0;
+    while (i + 1 < N - 1 && bound * (uint64_t)(N - i - 1) < (1ull << 24)) {
+        bound *= (uint64_t)(N - i - 1);
+        ++i;
+    }
+    return i;
+}
+
 // The same with n fixed at compile time: the loops unroll, shifts become
 // constants and the divisions of the unrank become multiplications. R is
 // the rank type: uint32_t up to n = 12, uint64_t beyond (16! < 2^45).
@@ -56,21 +85,33 @@ __host__ __device__ __forceinline__ R perm_rank_t(uint64_t key) {
     // c_i = number of values below s[i] not used before position i: the
     // popcount of the low s[i] bits of the still-unused set. The first
     // position has c_0 = s[0]; the last always has c = 0.
+    //
+    // The Horner sum is split in two: positions 0..kHi accumulate in `hi`,
+    // whose bound N (N-1) ... (N-kHi) stays below 2^24, the rest in `lo`;
+    // rank = hi * (product of the later radices) + lo. Every step is then a
+    // 24-bit multiply-add (full rate) instead of a 32-bit multiply.
     if constexpr (N <= 1) {
         return 0;
     } else {
+        constexpr int kHi = rank_split<N>();
         uint32_t unused = (1u << N) - 1u;
         const uint32_t v0 = (uint32_t)(key >> (4 * (N - 1))) & 15u;
-        R rank = (R)v0;
+        R hi = (R)v0, lo = 0;
+        R lo_radix = 1;
         unused ^= 1u << v0;
 #pragma unroll
         for (int i = 1; i < N - 1; ++i) {
             const uint32_t v = (uint32_t)(key >> (4 * (N - 1 - i))) & 15u;
             const uint32_t c = (uint32_t)__builtin_popcount(unused & ((1u << v) - 1u));
-            rank = rank * (R)(N - i) + (R)c;
+            if (i <= kHi) {
+                hi = mad24<R>(hi, (R)(N - i), (R)c);
+            } else {
+                lo = mad24<R>(lo, (R)(N - i), (R)c);
+                lo_radix *= (R)(N - i);
+            }
             unused ^= 1u << v;
         }
-        return rank;  // the last position's digit is 0 (radix 1)
+        return mad24<R>(hi, lo_radix, lo);  // the last position's digit is 0 (radix 1)
     }
 }
 

@@ -264,12 +264,15 @@ __global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
         cur[p] = 0;
         run[p] = 0;
     }
-    for (uint64_t base = lo; base < hi; base += (uint64_t)kBlock * kExpandIpt) {
+    // Every round but possibly the block's last is full: its body needs no
+    // per-state bounds checks.
+    auto round = [&](uint64_t base, auto guard) {
+        constexpr bool kGuard = decltype(guard)::value;
         Nibbles st[kExpandIpt];
 #pragma unroll
         for (int j = 0; j < kExpandIpt; ++j) {
             const uint64_t f = base + expand_slot(j);
-            st[j] = split_nibbles(f < hi ? frontier[f] : 0ull);
+            st[j] = split_nibbles(!kGuard || f < hi ? frontier[f] : 0ull);
         }
         for (int g = 0; g < k; ++g) {
             const GenSel sel = gsel[g];
@@ -277,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
 #pragma unroll
             for (int j = 0; j < kExpandIpt; ++j) {
                 const uint64_t f = base + expand_slot(j);
-                if (f >= hi) continue;
+                if (kGuard && f >= hi) continue;
                 const uint32_t r = perm_rank_t<N>(apply_gensel(st[j], sel));
                 o[f] = r;
 #pragma unroll
@@ -285,17 +288,20 @@ __global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
                     const uint32_t d = (r >> (p * kRadixBits)) & RankPasses<N>::mask(p);
                     if (p < CG_HIST_DIRECT_PASSES) {
                         atomicAdd(&s_h[p][d], 1u);
-                    } else if (d != cur[p]) {
-                        if (run[p]) atomicAdd(&s_h[p][cur[p]], run[p]);
-                        cur[p] = d;
-                        run[p] = 1;
                     } else {
-                        ++run[p];
+                        const bool chg = d != cur[p];
+                        if (chg) atomicAdd(&s_h[p][cur[p]], run[p]);  // run 0 before the first digit
+                        run[p] = chg ? 1u : run[p] + 1u;
+                        cur[p] = d;
                     }
                 }
             }
         }
-    }
+    };
+    const uint64_t kRound = (uint64_t)kBlock * kExpandIpt;
+    uint64_t base = lo;
+    for (; base + kRound <= hi; base += kRound) round(base, std::false_type{});
+    if (base < hi) round(base, std::true_type{});
 #pragma unroll
     for (int p = 0; p < kP; ++p)
         if (p >= CG_HIST_DIRECT_PASSES && run[p]) atomicAdd(&s_h[p][cur[p]], run[p]);

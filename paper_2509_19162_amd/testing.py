@@ -58,6 +58,15 @@ def sort(keys, bit_lo: int, bit_hi: int, stream=None):
     return keys
 
 
+def sort32(keys, bit_lo: int, bit_hi: int, stream=None):
+    """32-bit keys (an int32 tensor holding the bit patterns), sorted in place."""
+    import torch
+
+    tmp = torch.empty_like(keys)
+    _check(N.lib().cg_test_sort32(_dptr(keys), _dptr(tmp), keys.numel(), bit_lo, bit_hi, _stream(stream)))
+    return keys
+
+
 def dedup(sorted_keys, a, b, stream=None):
     import torch
 

@@ -20,7 +20,7 @@ def declared_functions():
     for h in ("cayleygrowth.h", "cayleygrowth_testing.h"):
         text = open(os.path.join(ROOT, "include", h)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        for m in re.finditer(r"\b(cg_[a-z_]+)\s*\(", text):
+        for m in re.finditer(r"\b(cg_[a-z0-9_]+)\s*\(", text):
             names.add(m.group(1))
     return names
 

@@ -82,6 +82,33 @@ def test_sort_heavy_duplicates(count, distinct, rng):
     assert np.array_equal(T.to_u64(t), _stable_sorted(keys, 4, 48))
 
 
+# the 32-bit sort (ranks of candidates, n <= 12) has tiles of 15360 keys
+SORT32_SIZES = [0, 1, 2, 65, 15359, 15360, 15361, 3 * 15360 + 7, 100_003, 1_048_613]
+
+
+@pytest.mark.parametrize("count", SORT32_SIZES)
+@pytest.mark.parametrize("lo,hi", [(0, 29), (0, 32), (3, 17), (8, 9)])
+def test_sort32_matches_stable_numpy(count, lo, hi, rng):
+    keys = rng.integers(0, 2 ** 32, size=count, dtype=np.uint64).astype(np.uint32)
+    t = torch.from_numpy(keys.view(np.int32).copy()).cuda()
+    T.sort32(t, lo, hi)
+    got = t.cpu().numpy().view(np.uint32)
+    digits = (keys.astype(np.uint64) >> np.uint64(lo)) & np.uint64((1 << (hi - lo)) - 1)
+    assert np.array_equal(got, keys[np.argsort(digits, kind="stable")])
+
+
+@pytest.mark.parametrize("count", [40_000, 2_000_000])
+@pytest.mark.parametrize("distinct", [1, 5, 3000])
+def test_sort32_duplicates_and_identity_passes(count, distinct, rng):
+    # ranks below 2^20 sorted on 32 bits: the top pass is the identity (and
+    # skipped for large arrays); many equal keys straddle tile borders
+    pool = rng.integers(0, 1 << 20, size=distinct, dtype=np.uint64).astype(np.uint32)
+    keys = pool[rng.integers(0, distinct, size=count)]
+    t = torch.from_numpy(keys.view(np.int32).copy()).cuda()
+    T.sort32(t, 0, 32)
+    assert np.array_equal(t.cpu().numpy().view(np.uint32), np.sort(keys, kind="stable"))
+
+
 def _np_dedup(s, a, b):
     u = np.unique(s)
     return np.setdiff1d(np.setdiff1d(u, a, assume_unique=True), b, assume_unique=True)
