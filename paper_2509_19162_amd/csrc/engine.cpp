@@ -333,12 +333,30 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
     uint64_t written = 0;
     const uint64_t key0 = pack_host(n, spec.start);
 
-    // generator selectors
+    // generator selectors, followed by each generator's first position
+    // from which it fixes every position
     std::vector<GenSel> hsel(k > 0 ? k : 1);
-    for (int g = 0; g < k; ++g) hsel[g] = make_gensel(n, spec.gens.data() + (size_t)g * n);
-    gsel_.ensure(sizeof(GenSel) * hsel.size());
-    CG_HIP(hipMemcpyAsync(gsel_.p, hsel.data(), sizeof(GenSel) * hsel.size(), hipMemcpyHostToDevice,
+    std::vector<uint8_t> hfix(hsel.size(), 0);
+    int moved = 0;  // Lehmer digits an incremental rank computes per state and all generators
+    for (int g = 0; g < k; ++g) {
+        const uint8_t *row = spec.gens.data() + (size_t)g * n;
+        hsel[g] = make_gensel(n, row);
+        for (int p = 0; p < n; ++p)
+            if (row[p] != p) hfix[g] = (uint8_t)(p + 1);
+        moved += std::min(std::max<int>(hfix[g], 2), n - 1) - 1;
+    }
+    const size_t sel_bytes = sizeof(GenSel) * hsel.size();
+    gsel_.ensure(sel_bytes + hfix.size());
+    CG_HIP(hipMemcpyAsync(gsel_.p, hsel.data(), sel_bytes, hipMemcpyHostToDevice, stream_));
+    CG_HIP(hipMemcpyAsync(gsel_.as<uint8_t>() + sel_bytes, hfix.data(), hfix.size(), hipMemcpyHostToDevice,
                           stream_));
+    // incremental ranks when the digits they compute, plus the parent's
+    // suffix sums (about two full ranks per state), stay under 90% of k
+    // full ranks
+    const uint8_t *d_gfix =
+        (n >= 6 && k > 0 && 10 * (moved + 2 * (n - 2)) <= 9 * k * (n - 2) && !std::getenv("CG_RANK_FULL"))
+            ? gsel_.as<uint8_t>() + sel_bytes
+            : nullptr;
 
     // layer storage
     std::vector<uint64_t> off;  // keep_all: offsets of the layers in the arena
@@ -473,7 +491,7 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             // candidates as 32-bit lexicographic ranks: half the bytes per
             // sort pass and only ceil(log2 n!) bits to sort
             uint32_t *c0 = cand0_.as<uint32_t>(), *c1 = cand1_.as<uint32_t>();
-            const uint32_t *sorted = expand_rank_sort(n, Ld, F, gsel_.as<GenSel>(), k, c0, c1, rank_bits, w_);
+            const uint32_t *sorted = expand_rank_sort(n, Ld, F, gsel_.as<GenSel>(), d_gfix, k, c0, c1, rank_bits, w_);
             uint32_t *scratch = sorted == c0 ? c1 : c0;
             const bool by_rank = !directed && rk_cur && rk_prev;
             if (by_rank)

@@ -206,15 +206,21 @@ __global__ __launch_bounds__(kBlock) void hist_kernel(Src src, uint32_t ntiles, 
 #define CG_EXPAND_IPT 4
 #endif
 constexpr int kExpandIpt = CG_EXPAND_IPT;  // frontier states per thread and round
+#ifndef CG_EXPAND_IPT_INCR
+#define CG_EXPAND_IPT_INCR 4
+#endif
+// the same with incremental ranks (each state also holds its suffix sums)
+constexpr int kExpandIptIncr = CG_EXPAND_IPT_INCR;
 // Frontier state j of the calling thread within a round of kBlock*kExpandIpt
 // states: consecutive per thread (CG_EXPAND_CONTIG, the default) or strided
 // across the block. Consecutive states of the sorted frontier share their
 // leading entries, so their candidates under one generator share high rank
 // digits: the runs the histograms merge before each LDS atomic get long
 // (S_12 pancake: expand 24.9 -> 15.7 ms).
+template <int IPT = kExpandIpt>
 __device__ __forceinline__ uint32_t expand_slot(int j) {
 #if CG_EXPAND_CONTIG
-    return threadIdx.x * kExpandIpt + (uint32_t)j;
+    return threadIdx.x * IPT + (uint32_t)j;
 #else
     return (uint32_t)j * kBlock + threadIdx.x;
 #endif
@@ -247,12 +253,89 @@ struct RankPasses {
     }
 };
 
+// Incremental ranks. The rank is sum_i c_i (n-1-i)! over the Lehmer digits
+// c_i (perm_rank.h). A generator that fixes every position from m on keeps
+// the set of values in front of each such position, so c_i of the
+// candidate equals c_i of its parent for i >= m: only the digits before m
+// are computed per candidate, and the parent's suffix sum of the rest is
+// computed once per frontier state and shared by all generators.
+constexpr uint32_t fact_c(int m) { return m <= 1 ? 1u : (uint32_t)m * fact_c(m - 1); }
+
+// v * (N-1)! for a value v < N; (N-1)! = f << s with f < 2^24 so that the
+// product is a 24-bit multiply (11! = 155925 << 8)
 template <int N>
+__device__ __forceinline__ uint32_t times_top_fact(uint32_t v) {
+    constexpr uint32_t f = fact_c(N - 1);
+    constexpr int s = f < (1u << 24) ? 0 : 8;
+    static_assert((f >> s) < (1u << 24) && ((f >> s) << s) == f, "top factorial splits");
+    return mad24<uint32_t>(v, f >> s, 0u) << s;
+}
+
+// sum of c_i(t) (N-1-i)! over the positions i < min(M, N-1) of key t
+template <int N, int M>
+__device__ __forceinline__ uint32_t rank_prefix(uint64_t t) {
+    constexpr int kEnd = M < N - 1 ? M : N - 1;
+    uint32_t unused = (1u << N) - 1u;
+    const uint32_t v0 = (uint32_t)(t >> (4 * (N - 1))) & 15u;
+    uint32_t acc = times_top_fact<N>(v0);
+    unused ^= 1u << v0;
+#pragma unroll
+    for (int i = 1; i < kEnd; ++i) {
+        const uint32_t v = (uint32_t)(t >> (4 * (N - 1 - i))) & 15u;
+        const uint32_t c = (uint32_t)__builtin_popcount(unused & ((1u << v) - 1u));
+        acc = mad24<uint32_t>(c, fact_c(N - 1 - i), acc);
+        unused ^= 1u << v;
+    }
+    return acc;
+}
+
+// suffix sums sum_{i=m}^{N-2} c_i(s) (N-1-i)! of key s for m = 2..N-2, to
+// dst[m-2]
+template <int N>
+__device__ __forceinline__ void rank_suffixes(uint64_t s, uint32_t *dst) {
+    if constexpr (N >= 4) {
+        uint32_t c[N];
+        uint32_t unused = (1u << N) - 1u;
+        unused ^= 1u << ((uint32_t)(s >> (4 * (N - 1))) & 15u);
+#pragma unroll
+        for (int i = 1; i < N - 1; ++i) {
+            const uint32_t v = (uint32_t)(s >> (4 * (N - 1 - i))) & 15u;
+            c[i] = (uint32_t)__builtin_popcount(unused & ((1u << v) - 1u));
+            unused ^= 1u << v;
+        }
+        uint32_t acc = 0;
+#pragma unroll
+        for (int m = N - 2; m >= 2; --m) {
+            acc = mad24<uint32_t>(c[m], fact_c(N - 1 - m), acc);
+            dst[m - 2] = acc;
+        }
+    }
+}
+
+// fn(integral_constant<int, M>) for the smallest M in [2, N] with m <= M
+template <int N, int M = 2, class Fn>
+__device__ __forceinline__ void with_prefix_len(int m, Fn &&fn) {
+    if constexpr (M >= N) {
+        fn(std::integral_constant<int, N>{});
+    } else {
+        if (m <= M)
+            fn(std::integral_constant<int, M>{});
+        else
+            with_prefix_len<N, M + 1>(m, fn);
+    }
+}
+
+// gfix (null: full ranks): per generator, the first position from which it
+// fixes every position (0 for the identity)
+template <int N, bool Incr>
 __global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
-    const uint64_t *__restrict__ frontier, uint64_t F, const GenSel *__restrict__ gsel, int k,
-    uint32_t *__restrict__ out, uint64_t per_block, unsigned long long *__restrict__ ghist) {
+    const uint64_t *__restrict__ frontier, uint64_t F, const GenSel *__restrict__ gsel,
+    const uint8_t *__restrict__ gfix, int k, uint32_t *__restrict__ out, uint64_t per_block,
+    unsigned long long *__restrict__ ghist) {
+    constexpr int kIpt = Incr ? kExpandIptIncr : kExpandIpt;
     constexpr int kP = RankPasses<N>::passes;
     static_assert(kP <= kMaxPasses, "rank passes");
+    constexpr int kSufRows = N > 4 ? N - 3 : 1;  // suffix sums for m = 2..N-2
     __shared__ uint32_t s_h[kMaxPasses][kRadix];
     for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kBlock) (&s_h[0][0])[i] = 0;
     __syncthreads();
@@ -268,37 +351,56 @@ __global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
     // per-state bounds checks.
     auto round = [&](uint64_t base, auto guard) {
         constexpr bool kGuard = decltype(guard)::value;
-        Nibbles st[kExpandIpt];
+        Nibbles st[kIpt];
+        // per state, in registers: every use below indexes it with constants
+        uint32_t suf[kIpt][Incr ? kSufRows : 1];
 #pragma unroll
-        for (int j = 0; j < kExpandIpt; ++j) {
-            const uint64_t f = base + expand_slot(j);
-            st[j] = split_nibbles(!kGuard || f < hi ? frontier[f] : 0ull);
+        for (int j = 0; j < kIpt; ++j) {
+            const uint64_t f = base + expand_slot<kIpt>(j);
+            const uint64_t key = !kGuard || f < hi ? frontier[f] : 0ull;
+            st[j] = split_nibbles(key);
+            if constexpr (Incr) rank_suffixes<N>(key, suf[j]);
         }
         for (int g = 0; g < k; ++g) {
             const GenSel sel = gsel[g];
             uint32_t *o = out + (uint64_t)g * F;
+            auto body = [&](auto MM) {
+                constexpr int M = decltype(MM)::value;
 #pragma unroll
-            for (int j = 0; j < kExpandIpt; ++j) {
-                const uint64_t f = base + expand_slot(j);
-                if (kGuard && f >= hi) continue;
-                const uint32_t r = perm_rank_t<N>(apply_gensel(st[j], sel));
-                o[f] = r;
-#pragma unroll
-                for (int p = 0; p < kP; ++p) {
-                    const uint32_t d = (r >> (p * kRadixBits)) & RankPasses<N>::mask(p);
-                    if (p < CG_HIST_DIRECT_PASSES) {
-                        atomicAdd(&s_h[p][d], 1u);
+                for (int j = 0; j < kIpt; ++j) {
+                    const uint64_t f = base + expand_slot<kIpt>(j);
+                    if (kGuard && f >= hi) continue;
+                    const uint64_t t = apply_gensel(st[j], sel);
+                    uint32_t r;
+                    if constexpr (!Incr) {
+                        r = perm_rank_t<N>(t);
+                    } else if constexpr (M <= N - 2) {
+                        r = rank_prefix<N, M>(t) + suf[j][M - 2];
                     } else {
-                        const bool chg = d != cur[p];
-                        if (chg) atomicAdd(&s_h[p][cur[p]], run[p]);  // run 0 before the first digit
-                        run[p] = chg ? 1u : run[p] + 1u;
-                        cur[p] = d;
+                        r = rank_prefix<N, M>(t);
+                    }
+                    o[f] = r;
+#pragma unroll
+                    for (int p = 0; p < kP; ++p) {
+                        const uint32_t d = (r >> (p * kRadixBits)) & RankPasses<N>::mask(p);
+                        if (p < CG_HIST_DIRECT_PASSES) {
+                            atomicAdd(&s_h[p][d], 1u);
+                        } else {
+                            const bool chg = d != cur[p];
+                            if (chg) atomicAdd(&s_h[p][cur[p]], run[p]);  // run 0 before the first digit
+                            run[p] = chg ? 1u : run[p] + 1u;
+                            cur[p] = d;
+                        }
                     }
                 }
-            }
+            };
+            if constexpr (Incr)
+                with_prefix_len<N>((int)gfix[g], body);  // uniform: one branch chain per generator
+            else
+                body(std::integral_constant<int, N>{});
         }
     };
-    const uint64_t kRound = (uint64_t)kBlock * kExpandIpt;
+    const uint64_t kRound = (uint64_t)kBlock * kIpt;
     uint64_t base = lo;
     for (; base + kRound <= hi; base += kRound) round(base, std::false_type{});
     if (base < hi) round(base, std::true_type{});
@@ -783,8 +885,8 @@ uint32_t *radix_sort32(uint32_t *keys, uint32_t *tmp, uint64_t count, int bit_lo
     return run_sort(src, count, tmp, keys, bit_lo, bit_hi, w, false, 4.0 * (double)count, keys);
 }
 
-uint32_t *expand_rank_sort(int n, const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,
-                           uint32_t *buf0, uint32_t *buf1, int rank_bits, PipeWork &w) {
+uint32_t *expand_rank_sort(int n, const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, const uint8_t *d_gfix,
+                           int k, uint32_t *buf0, uint32_t *buf1, int rank_bits, PipeWork &w) {
     const uint64_t C = F * (uint64_t)k;
     if (C == 0) return buf0;
     w.ensure_status(sort_status_words(C));
@@ -794,8 +896,9 @@ uint32_t *expand_rank_sort(int n, const uint64_t *frontier, uint64_t F, const Ge
                        w.tickets(), 32u);
     CG_HIP(hipGetLastError());
     if (w.prof) w.prof->end(K_AUX, 0, 0);
-    // rounds of kBlock*kExpandIpt states; at most 4096 blocks
-    const uint64_t round = (uint64_t)kBlock * kExpandIpt;
+    // rounds of kBlock*ipt states; at most 4096 blocks
+    const bool incr = d_gfix && n >= 6;
+    const uint64_t round = (uint64_t)kBlock * (incr ? kExpandIptIncr : kExpandIpt);
     const uint64_t rounds = (F + round - 1) / round;
     const uint64_t blocks = rounds < 4096 ? rounds : 4096;
     const uint64_t per_block = ((rounds + blocks - 1) / blocks) * round;
@@ -805,8 +908,12 @@ uint32_t *expand_rank_sort(int n, const uint64_t *frontier, uint64_t F, const Ge
         constexpr int N = decltype(NN)::value;
         // the kernel's histograms follow the bits of S_N's ranks
         if (rank_bits != RankPasses<N>::bits()) throw Error(-1, "rank bits differ from those of n!");
-        hipLaunchKernelGGL(expand_rank_hist_kernel<N>, dim3(grid), dim3(kBlock), 0, w.stream, frontier, F,
-                           d_gsel, k, buf0, per_block, hist);
+        if (incr)
+            hipLaunchKernelGGL((expand_rank_hist_kernel<N, true>), dim3(grid), dim3(kBlock), 0, w.stream, frontier,
+                               F, d_gsel, d_gfix, k, buf0, per_block, hist);
+        else
+            hipLaunchKernelGGL((expand_rank_hist_kernel<N, false>), dim3(grid), dim3(kBlock), 0, w.stream, frontier,
+                               F, d_gsel, (const uint8_t *)nullptr, k, buf0, per_block, hist);
     });
     CG_HIP(hipGetLastError());
     if (w.prof) w.prof->end(K_EXPAND, 8.0 * (double)F + 4.0 * (double)C, (double)C);

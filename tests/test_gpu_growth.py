@@ -38,6 +38,26 @@ def test_families_match_oracle(fam, n, oracle_c):
     assert r.sizes == expected and r.status == rc == 0
 
 
+@pytest.mark.parametrize("full", [False, True], ids=["incremental", "full"])
+@pytest.mark.parametrize("fam,n", [("pancake", 8), ("coxeter", 9), ("star", 7), ("lrx", 8), ("all_transpositions", 7),
+                                   ("three_cycles", 6)])
+def test_incremental_and_full_ranks(fam, n, full, oracle_c, monkeypatch):
+    # candidates' ranks reuse the parent's Lehmer digits past each
+    # generator's last moved position, or (CG_RANK_FULL) are computed whole
+    if full:
+        monkeypatch.setenv("CG_RANK_FULL", "1")
+    gens = I.family(fam, n)
+    expected, rc, _ = oracle_c.growth(n, gens)
+    r = api.growth_ex(n, gens, keep_all_layers=True, export_layers=math.factorial(n))
+    assert r.sizes == expected and r.status == rc == 0
+    if full:
+        monkeypatch.delenv("CG_RANK_FULL")
+        other = api.growth_ex(n, gens, keep_all_layers=True, export_layers=math.factorial(n))
+        assert other.sizes == r.sizes
+        for a, b in zip(other.layers, r.layers):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
 @pytest.mark.parametrize("n", [10, 11, 12])
 def test_closed_forms_beyond_the_python_oracle(n):
     assert api.growth(n, I.coxeter(n), max_layers=100) == mahonian(n)
