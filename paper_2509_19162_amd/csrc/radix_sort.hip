@@ -751,7 +751,7 @@ template <class Src>
 typename Src::Key *run_sort(const Src &first_src, uint64_t count, typename Src::Key *buf0,
                             typename Src::Key *buf1, int bit_lo, int bit_hi, PipeWork &w, bool fused_first,
                             double first_read_bytes, const typename Src::Key *array_in,
-                            bool hist_ready = false) {
+                            bool hist_ready = false, bool skip_check = true) {
     using K = typename Src::Key;
     constexpr double kb = (double)sizeof(K);
     const PassDesc pd = make_passes(bit_lo, bit_hi);
@@ -784,7 +784,7 @@ typename Src::Key *run_sort(const Src &first_src, uint64_t count, typename Src::
     // batched group).
     int keep[kMaxPasses];
     int nkeep = 0;
-    if (count >= kSkipCheckMin) {
+    if (skip_check && count >= kSkipCheckMin) {
         unsigned long long h[kMaxPasses * kRadix];
         CG_HIP(hipMemcpyAsync(h, hist, sizeof(unsigned long long) * kRadix * pd.passes, hipMemcpyDeviceToHost,
                               w.stream));
@@ -919,7 +919,10 @@ uint32_t *expand_rank_sort(int n, const uint64_t *frontier, uint64_t F, const Ge
     if (w.prof) w.prof->end(K_EXPAND, 8.0 * (double)F + 4.0 * (double)C, (double)C);
     if (rank_bits <= 0) return buf0;
     const ArraySrcT<uint32_t> src{buf0, C};
-    return run_sort(src, C, buf1, buf0, 0, rank_bits, w, false, 4.0 * (double)C, buf0, true);
+    // Ranks of a large layer's candidates spread over [0, n!): no pass is
+    // the identity, so the histograms are not read back (no host sync); a
+    // pass that is one anyway runs as an ordinary pass.
+    return run_sort(src, C, buf1, buf0, 0, rank_bits, w, false, 4.0 * (double)C, buf0, true, false);
 }
 
 uint64_t *expand_sort(const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,
