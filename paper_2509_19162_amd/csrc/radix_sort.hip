@@ -74,6 +74,14 @@ constexpr int kTile = TileOf<uint64_t>::tile;  // the shortest tile: sizes look-
 #define CG_SORT_ROWS 1
 #endif
 constexpr int kRows = CG_SORT_ROWS;  // rows ranked per LDS round trip
+// Look-back passes with persistent blocks, per key width (32-bit tiles are
+// register-bound: the tile loop would push them into spills)
+#ifndef CG_SORT_PERSIST32
+#define CG_SORT_PERSIST32 0
+#endif
+#ifndef CG_SORT_PERSIST64
+#define CG_SORT_PERSIST64 1
+#endif
 #ifndef CG_SORT_HALF_MASK
 #define CG_SORT_HALF_MASK 1  // peer masks set and cleared by 32-bit halves
 #endif
@@ -471,15 +479,26 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
                   "match words fit in the reorder buffer");
     static_assert(kIpt % kRows == 0, "rows per group divide the rows per thread");
 
-    const uint32_t tid = threadIdx.x;
+    constexpr bool kPersist = Lookback && (sizeof(K) == 4 ? CG_SORT_PERSIST32 : CG_SORT_PERSIST64);
+    if (Lookback && threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+    // With look-back the blocks are persistent: each takes tiles in ticket
+    // order until the tickets run out (every block ends on a ticket past the
+    // last tile), which saves a block launch per tile. Tickets are only
+    // drawn by running blocks for the tile they start next, so the smallest
+    // unfinished ticket is always some block's current tile: every wait ends.
+    const uint32_t ntiles = src.tiles();
+    for (;;) {
+    uint32_t tid = threadIdx.x;
+    // an opaque copy of the thread index: addresses derived from it are
+    // computed per tile, not hoisted out of the tile loop into registers
+    if constexpr (kPersist) __asm__ volatile("" : "+v"(tid));
     const uint32_t lane = tid & (kWave - 1);
     const uint32_t wave = tid / kWave;
-
-    if (Lookback && tid == 0) s_tile = atomicAdd(ticket, 1u);
     for (int i = tid; i < kWv * kRadix; i += kBlk) (&s_cnt[0][0])[i] = 0;
     for (int i = tid; i < kRows * kWv * kRadix; i += kBlk) (&s_match[0][0][0])[i] = 0;
     __syncthreads();
     const uint32_t tile = Lookback ? s_tile : blockIdx.x;
+    if (kPersist && tile >= ntiles) break;  // same for the whole block
     const auto T = src.tile(tile);
     const uint32_t nvalid = T.n;
 
@@ -645,6 +664,12 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
             else
                 atomicOr(err, 2u);  // inconsistent offsets: never write out of bounds
         }
+    }
+    if constexpr (!kPersist) break;
+    // the next ticket only now: a ticket held while another tile finishes
+    // would stall the look-backs of every later tile
+    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();  // the next ticket is visible and the reorder buffer is free
     }
 }
 
@@ -834,7 +859,21 @@ typename Src::Key *run_sort(const Src &first_src, uint64_t count, typename Src::
                                0u, w.err(), w.toff.as<const uint64_t>());
         } else {
             const uint32_t epoch = w.next_epoch();
-            hipLaunchKernelGGL((onesweep_kernel<S, true>), dim3(nt), dim3(TileOf<typename S::Key>::block), 0,
+            uint32_t grid = nt;
+            if (sizeof(typename S::Key) == 4 ? CG_SORT_PERSIST32 : CG_SORT_PERSIST64) {
+            // persistent blocks: as many as can be resident at once
+            static const uint32_t resident = [] {
+                int per_cu = 0, dev = 0, cus = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, onesweep_kernel<S, true>,
+                                                                  TileOf<typename S::Key>::block, 0) != hipSuccess ||
+                    hipGetDevice(&dev) != hipSuccess ||
+                    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+                    return 0u;
+                return (uint32_t)(per_cu > 0 ? per_cu : 1) * (uint32_t)(cus > 0 ? cus : 1);
+            }();
+            if (resident && resident < grid) grid = resident;
+            }
+            hipLaunchKernelGGL((onesweep_kernel<S, true>), dim3(grid), dim3(TileOf<typename S::Key>::block), 0,
                                w.stream, src, cur_out, count,
                                pd.shift[p], pd.mask[p], base + p * kRadix, w.status.as<uint64_t>(), w.tickets() + p,
                                epoch, w.err(), (const uint64_t *)nullptr);
