@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void hist_kernel(Src src, uint32_t ntiles, 
 #endif
 constexpr int kExpandIpt = CG_EXPAND_IPT;  // frontier states per thread and round
 #ifndef CG_EXPAND_IPT_INCR
-#define CG_EXPAND_IPT_INCR 4
+#define CG_EXPAND_IPT_INCR 6
 #endif
 // the same with incremental ranks (each state also holds its suffix sums)
 constexpr int kExpandIptIncr = CG_EXPAND_IPT_INCR;
