@@ -117,7 +117,7 @@ Engine::Engine(hipStream_t user_stream) {
                       &vis_[1], &rk_[0], &rk_[1], &rk_[2]})
         b->stream = stream_;
     prof_.stream = stream_;
-    CG_HIP(hipHostMalloc((void **)&host_small_, 64, hipHostMallocDefault));
+    CG_HIP(hipHostMalloc((void **)&host_small_, kHostSmallBytes, hipHostMallocDefault));
 }
 
 Engine::~Engine() {
@@ -137,12 +137,21 @@ Engine::~Engine() {
 }
 
 uint64_t Engine::read_counter() {
-    CG_HIP(hipMemcpyAsync(host_small_, w_.counter(), sizeof(uint64_t), hipMemcpyDeviceToHost, stream_));
-    CG_HIP(hipMemcpyAsync(host_small_ + 1, w_.err(), sizeof(uint32_t), hipMemcpyDeviceToHost, stream_));
+    // the error flag and the counter lie in one small device buffer: one
+    // copy brings both
+    const char *lo = (const char *)w_.err();
+    const size_t span = (size_t)((const char *)(w_.counter() + 1) - lo);
+    static_assert(kHostSmallBytes >= 256, "the flag-to-counter span fits");
+    if ((const char *)w_.counter() < lo || span > kHostSmallBytes) throw Error(-1, "counter layout");
+    CG_HIP(hipMemcpyAsync(host_small_, lo, span, hipMemcpyDeviceToHost, stream_));
     CG_HIP(hipStreamSynchronize(stream_));
-    if (((uint32_t *)(host_small_ + 1))[0] != 0)
-        throw Error(CG_E_DEVICE, "kernel error flag set (look-back bound or offset check)");
-    return host_small_[0];
+    const char *h = (const char *)host_small_;
+    uint32_t err;
+    uint64_t count;
+    std::memcpy(&err, h, sizeof err);
+    std::memcpy(&count, h + ((const char *)w_.counter() - lo), sizeof count);
+    if (err != 0) throw Error(CG_E_DEVICE, "kernel error flag set (look-back bound or offset check)");
+    return count;
 }
 
 void Engine::export_layer(const JobSpec &spec, const uint64_t *d_keys, uint64_t count,

@@ -63,7 +63,8 @@ private:
     DevBuf gsel_, cand0_, cand1_, lay_[3], arena_, stage_, chunk_hist_, vis_[2];
     DevBuf rk_[3];  // ranked runs: 32-bit ranks of layers d-1, d, d+1
     class WgRunner *wg_ = nullptr;  // small-job engine (created on first use)
-    uint64_t *host_small_ = nullptr;  // pinned: counter + error flag
+    static constexpr size_t kHostSmallBytes = 512;
+    uint64_t *host_small_ = nullptr;  // pinned: error flag .. counter
 };
 
 void fill_kstats(const Profiler &p, cg_result_t *res);
