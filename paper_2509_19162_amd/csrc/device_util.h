@@ -138,6 +138,7 @@ __device__ __forceinline__ int lb_round(const uint64_t *base, uint64_t stride, i
 // round trips. Tiles publish in ticket order, so every tile waited on is
 // already running; the wait is still bounded: on overrun the error flag is
 // raised and the (then meaningless) partial sum returned.
+template <int kFirst = kLbDepth, int kFar = kLbDepthFar>
 __device__ __forceinline__ uint64_t lb_lookback(const uint64_t *base, uint64_t stride,
                                                 uint32_t tile, uint32_t epoch,
                                                 uint32_t *err) {
@@ -147,8 +148,8 @@ __device__ __forceinline__ uint64_t lb_lookback(const uint64_t *base, uint64_t s
     bool first = true;
     while (t >= 0) {
         bool done = false;
-        const int used = first ? lb_round<kLbDepth>(base, stride, t, epoch, excl, done)
-                               : lb_round<kLbDepthFar>(base, stride, t, epoch, excl, done);
+        const int used = first ? lb_round<kFirst>(base, stride, t, epoch, excl, done)
+                               : lb_round<kFar>(base, stride, t, epoch, excl, done);
         if (done) break;
         t -= used;
         if (used == 0) {

@@ -76,6 +76,14 @@ constexpr int kTile = TileOf<uint64_t>::tile;  // the shortest tile: sizes look-
 constexpr int kRows = CG_SORT_ROWS;  // rows ranked per LDS round trip
 // Look-back passes with persistent blocks, per key width (32-bit tiles are
 // register-bound: the tile loop would push them into spills)
+// look-back depths (first round, later rounds) of the 64-bit passes, whose
+// tiles are shorter; the 32-bit passes use the defaults of device_util.h
+#ifndef CG_LB_DEPTH64
+#define CG_LB_DEPTH64 1
+#endif
+#ifndef CG_LB_DEPTH_FAR64
+#define CG_LB_DEPTH_FAR64 3
+#endif
 #ifndef CG_SORT_PERSIST32
 #define CG_SORT_PERSIST32 0
 #endif
@@ -607,7 +615,9 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
                 lb_store(my, lb_word(epoch, kFlagInclusive, pub));
             } else {
                 lb_store(my, lb_word(epoch, kFlagAggregate, pub));
-                excl = lb_lookback(status + d, kRadix, tile, epoch, err);
+                excl = sizeof(K) == 4 ? lb_lookback(status + d, kRadix, tile, epoch, err)
+                                      : lb_lookback<CG_LB_DEPTH64, CG_LB_DEPTH_FAR64>(status + d, kRadix, tile,
+                                                                                      epoch, err);
                 lb_store(my, lb_word(epoch, kFlagInclusive, excl + pub));
             }
             s_gstart[d] = (uint64_t)digit_base[d] + excl;
