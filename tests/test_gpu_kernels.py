@@ -109,6 +109,25 @@ def test_sort32_duplicates_and_identity_passes(count, distinct, rng):
     assert np.array_equal(t.cpu().numpy().view(np.uint32), np.sort(keys, kind="stable"))
 
 
+@pytest.mark.parametrize("count,lo,hi", [(12_000_003, 4, 64), (9_437_185, 20, 60)])
+def test_sort_large_persistent_blocks(count, lo, hi):
+    # 64-bit passes run persistent blocks; past ~1500 resident blocks of
+    # 4096-key tiles every block takes several tiles by ticket
+    rng = np.random.default_rng(count)
+    keys = rng.integers(0, 2 ** 63, size=count, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, size=count, dtype=np.uint64)
+    t = T.from_u64(keys)
+    T.sort(t, lo, hi)
+    assert np.array_equal(T.to_u64(t), _stable_sorted(keys, lo, hi))
+
+
+def test_sort32_large():
+    rng = np.random.default_rng(32)
+    keys = rng.integers(0, 479001600, size=30_000_001, dtype=np.uint64).astype(np.uint32)
+    t = torch.from_numpy(keys.view(np.int32).copy()).cuda()
+    T.sort32(t, 0, 29)
+    assert np.array_equal(t.cpu().numpy().view(np.uint32), np.sort(keys, kind="stable"))
+
+
 def _np_dedup(s, a, b):
     u = np.unique(s)
     return np.setdiff1d(np.setdiff1d(u, a, assume_unique=True), b, assume_unique=True)
