@@ -169,6 +169,22 @@ def test_pancake_s12_full_growth_matches_oracle():
     assert sum(r.sizes) == math.factorial(12)
 
 
+def test_pancake_s12_full_run_first_layers_match_oracle(oracle_c):
+    """The full S_12 growth (all layers kept, as benchmarked) exports its
+    first states; layers 0..6 (622,438 states) must equal the oracle's."""
+    r = api.growth_ex(12, I.pancake(12), keep_all_layers=True, export_layers=700_000)
+    assert r.status == N.CG_OK and sum(r.sizes) == math.factorial(12)
+    sizes, rc, states = oracle_c.growth(12, I.pancake(12), max_layers=7, with_states=True)
+    assert r.sizes[:7] == sizes
+    off = 0
+    for d, sz in enumerate(sizes):
+        got = np.asarray(r.layers[d])
+        exp = states[off: off + sz]
+        off += sz
+        key = lambda a: np.unique(np.asarray(a, dtype=np.uint8).reshape(-1, 12), axis=0)
+        assert np.array_equal(key(got), key(exp)), d
+
+
 def test_lrx16_until_frontier_exceeds_2_31():
     """S_16 with L, R, X: every layer up to the first one larger than 2^31.
     The oracle's prefix (layers up to the first one above 2^26) is matched
