@@ -1,4 +1,5 @@
-// Stable LSD radix sort of 64-bit state keys on a bit range, for gfx950.
+// Stable LSD radix sort, for gfx950, of 64-bit state keys on a bit range and
+// of 32-bit lexicographic ranks (candidates of n <= 12 states).
 //
 // The growth step needs the candidates of a layer in sorted order so that
 // repeats become neighbours and the set difference against the two previous
@@ -8,19 +9,23 @@
 //
 // Structure (one-sweep LSD):
 //   1. hist    one read of the keys computes the 8-bit digit histograms of
-//              every pass at once (LDS counters, one flush per block);
+//              every pass at once (LDS counters, one flush per block); for
+//              ranks the expand kernel counts them while it writes them;
 //   2. scan    exclusive prefix of each pass's 256 digit counts;
-//   3. pass p  each 4096-key tile ranks its keys per digit within each
-//              wave64 (an LDS word per digit collects the mask of lanes
-//              sharing it, v_mbcnt gives the rank below), publishes its per-digit counts
-//              as decoupled look-back words, reads the exclusive prefix of
-//              the tiles before it, reorders the tile in LDS by digit and
-//              writes runs of equal digits to consecutive addresses.
-// Each pass reads and writes every key once (16 bytes per key).
+//   3. pass p  each tile (4096 64-bit or 15360 32-bit keys) ranks its keys
+//              per digit within each wave64 (an LDS word per digit collects
+//              the mask of lanes sharing it, v_mbcnt gives the rank below),
+//              publishes its per-digit counts as decoupled look-back words,
+//              reads the exclusive prefix of the tiles before it, reorders
+//              the tile in LDS by digit and writes runs of equal digits to
+//              consecutive addresses. 64-bit passes run persistent blocks
+//              that take tiles by ticket.
+// Each pass reads and writes every key once (8 or 16 bytes per key).
 //
 // The first pass of expand_sort() regenerates the candidates from the
 // frontier (permute-expand fused into the pass), so the unsorted candidate
-// array is never written.
+// array is never written; expand_rank_sort() writes the candidates' ranks
+// once, with the histograms of every pass.
 #include <cstdlib>
 #include <type_traits>
 
