@@ -50,7 +50,9 @@ __host__ __device__ __forceinline__ uint64_t perm_unrank(uint32_t rank, int n) {
 
 // a * b + c for a, b < 2^24 (both factors of every use below are): a 24-bit
 // multiply-add for 32-bit ranks, a plain one for 64-bit ranks (the product
-// may exceed 32 bits there).
+// may exceed 32 bits there). On the device b goes through a scalar
+// register, so it must be the same in every lane (every use passes a
+// radix or factorial fixed at compile time).
 template <class R>
 __host__ __device__ __forceinline__ R mad24(R a, R b, R c) {
 #ifdef __HIP_DEVICE_COMPILE__
