@@ -43,6 +43,9 @@ constexpr int kWaves = kBlock / kWave;
 constexpr int kIpt = CG_DEDUP_IPT;
 constexpr int kTile = kBlock * kIpt;  // 4096 candidates per dedup tile by default
 constexpr int kRefIpt = 4;            // reference keys per thread loaded with the tile
+#ifndef CG_DEDUP_LOCKSTEP
+#define CG_DEDUP_LOCKSTEP 1  // the tile's first references searched in lockstep
+#endif
 // largest candidate array looked up from the reference side (4 MB of u32)
 constexpr uint64_t kMarkMaxCandidates = 1u << 20;
 
@@ -203,9 +206,34 @@ __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
         const uint32_t lb = pos + (s_keys[pad(pos)] < key ? 1u : 0u);
         if (lb < nvalid && s_keys[pad(lb)] == key) s_kill[lb] = 1;
     };
+#if CG_DEDUP_LOCKSTEP
+    // The first kRefIpt references of each thread search together: the
+    // tile is padded to kTile (a power of two) with all-ones keys, so a
+    // fixed log2(kTile)-step lower bound over it needs no length and the
+    // searches' LDS probes overlap instead of following one another.
+    static_assert((kTile & (kTile - 1)) == 0, "tile length is a power of two");
+    {
+        uint32_t pos[kRefIpt];
+#pragma unroll
+        for (int u = 0; u < kRefIpt; ++u) pos[u] = 0;
+#pragma unroll
+        for (uint32_t step = kTile / 2; step >= 1; step >>= 1) {
+#pragma unroll
+            for (int u = 0; u < kRefIpt; ++u)
+                pos[u] = s_keys[pad(pos[u] + step - 1)] < ref[u] ? pos[u] + step : pos[u];
+        }
+#pragma unroll
+        for (int u = 0; u < kRefIpt; ++u) {
+            const uint32_t lb = pos[u] + (s_keys[pad(pos[u])] < ref[u] ? 1u : 0u);
+            if ((uint64_t)u * kBlock + tid < n_ref && lb < nvalid && s_keys[pad(lb)] == ref[u])
+                s_kill[lb] = 1;
+        }
+    }
+#else
 #pragma unroll
     for (int u = 0; u < kRefIpt; ++u)
         if ((uint64_t)u * kBlock + tid < n_ref) mark(ref[u]);
+#endif
     for (uint64_t t = (uint64_t)kRefIpt * kBlock + tid; t < n_ref; t += kBlock) mark(ref_at(t));
     __syncthreads();
 
