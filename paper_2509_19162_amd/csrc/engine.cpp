@@ -354,11 +354,19 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             if (row[p] != p) hfix[g] = (uint8_t)(p + 1);
         moved += std::min(std::max<int>(hfix[g], 2), n - 1) - 1;
     }
+    // then, at the next 4-byte boundary, each generator's n source shifts:
+    // entry i of candidate s.g is the nibble of s at bit 4(n-1-g[i])
+    std::vector<uint32_t> hsh(hsel.size() * (size_t)n, 0);
+    for (int g = 0; g < k; ++g)
+        for (int i = 0; i < n; ++i) hsh[(size_t)g * n + i] = 4u * (uint32_t)(n - 1 - spec.gens[(size_t)g * n + i]);
     const size_t sel_bytes = sizeof(GenSel) * hsel.size();
-    gsel_.ensure(sel_bytes + hfix.size());
+    const size_t sh_off = sel_bytes + ((hfix.size() + 3) & ~(size_t)3);
+    gsel_.ensure(sh_off + hsh.size() * sizeof(uint32_t));
     CG_HIP(hipMemcpyAsync(gsel_.p, hsel.data(), sel_bytes, hipMemcpyHostToDevice, stream_));
     CG_HIP(hipMemcpyAsync(gsel_.as<uint8_t>() + sel_bytes, hfix.data(), hfix.size(), hipMemcpyHostToDevice,
                           stream_));
+    CG_HIP(hipMemcpyAsync(gsel_.as<uint8_t>() + sh_off, hsh.data(), hsh.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice, stream_));
     // incremental ranks when the digits they compute, plus the parent's
     // suffix sums (about two full ranks per state), stay under 90% of k
     // full ranks

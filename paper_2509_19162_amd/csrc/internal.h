@@ -175,9 +175,10 @@ uint64_t *radix_sort(uint64_t *keys, uint64_t *tmp, uint64_t count, int bit_lo,
 // Expands frontier[0..F) into the 32-bit ranks of the k*F candidates
 // (n <= 12) while counting the digits of every pass, then sorts them on
 // bits [0, rank_bits). Returns buf0 or buf1 (each k*F words). d_gfix
-// (device, k bytes, or null for full ranks): per generator, the first
-// position from which it fixes every position; the ranks then reuse the
-// parent's Lehmer digits from there on.
+// (device, or null for full ranks): k bytes, per generator the first
+// position from which it fixes every position (the ranks then reuse the
+// parent's Lehmer digits from there on), followed at the next 4-byte
+// boundary by k*n uint32 source shifts 4(n-1-g[i]).
 uint32_t *expand_rank_sort(int n, const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, const uint8_t *d_gfix,
                            int k, uint32_t *buf0, uint32_t *buf1, int rank_bits, PipeWork &w);
 // The same for 32-bit keys (candidates under their lexicographic rank).

@@ -292,6 +292,31 @@ __device__ __forceinline__ uint32_t times_top_fact(uint32_t v) {
     return mad24<uint32_t>(v, f >> s, 0u) << s;
 }
 
+// The same for t = s.g read straight from the parent s: entry i of t is
+// the nibble of s at bit sh[i] (sh uniform across the wave).
+__device__ __forceinline__ uint32_t nibble_at(uint32_t lo, uint32_t hi, uint32_t sh) {
+    // sh is uniform: one select of the half, one bit-field extract
+    return __builtin_amdgcn_ubfe(sh < 32u ? lo : hi, sh & 31u, 4u);
+}
+
+template <int N, int M>
+__device__ __forceinline__ uint32_t rank_prefix_from(uint64_t s, const uint32_t *__restrict__ sh) {
+    constexpr int kEnd = M < N - 1 ? M : N - 1;
+    const uint32_t lo = (uint32_t)s, hi = (uint32_t)(s >> 32);
+    uint32_t unused = (1u << N) - 1u;
+    const uint32_t v0 = nibble_at(lo, hi, sh[0]);
+    uint32_t acc = times_top_fact<N>(v0);
+    unused ^= 1u << v0;
+#pragma unroll
+    for (int i = 1; i < kEnd; ++i) {
+        const uint32_t v = nibble_at(lo, hi, sh[i]);
+        const uint32_t c = (uint32_t)__builtin_popcount(unused & ((1u << v) - 1u));
+        acc = mad24<uint32_t>(c, fact_c(N - 1 - i), acc);
+        unused ^= 1u << v;
+    }
+    return acc;
+}
+
 // sum of c_i(t) (N-1-i)! over the positions i < min(M, N-1) of key t
 template <int N, int M>
 __device__ __forceinline__ uint32_t rank_prefix(uint64_t t) {
@@ -355,6 +380,9 @@ __global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
     unsigned long long *__restrict__ ghist) {
     constexpr int kIpt = Incr ? kExpandIptIncr : kExpandIpt;
     constexpr int kP = RankPasses<N>::passes;
+    // the source shifts follow the k fix positions at the next 4-byte boundary
+    const uint32_t *__restrict__ gsh =
+        Incr ? reinterpret_cast<const uint32_t *>(gfix + (((uint32_t)k + 3u) & ~3u)) : nullptr;
     static_assert(kP <= kMaxPasses, "rank passes");
     constexpr int kSufRows = N > 4 ? N - 3 : 1;  // suffix sums for m = 2..N-2
     __shared__ uint32_t s_h[kMaxPasses][kRadix];
@@ -372,18 +400,24 @@ __global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
     // per-state bounds checks.
     auto round = [&](uint64_t base, auto guard) {
         constexpr bool kGuard = decltype(guard)::value;
-        Nibbles st[kIpt];
+        // full ranks permute the split state; incremental ones read the
+        // few entries they need straight from the parent's key
+        Nibbles st[Incr ? 1 : kIpt];
+        uint64_t sk[Incr ? kIpt : 1];
         // per state, in registers: every use below indexes it with constants
         uint32_t suf[kIpt][Incr ? kSufRows : 1];
 #pragma unroll
         for (int j = 0; j < kIpt; ++j) {
             const uint64_t f = base + expand_slot<kIpt>(j);
             const uint64_t key = !kGuard || f < hi ? frontier[f] : 0ull;
-            st[j] = split_nibbles(key);
-            if constexpr (Incr) rank_suffixes<N>(key, suf[j]);
+            if constexpr (Incr) {
+                sk[j] = key;
+                rank_suffixes<N>(key, suf[j]);
+            } else {
+                st[j] = split_nibbles(key);
+            }
         }
         for (int g = 0; g < k; ++g) {
-            const GenSel sel = gsel[g];
             uint32_t *o = out + (uint64_t)g * F;
             auto body = [&](auto MM) {
                 constexpr int M = decltype(MM)::value;
@@ -391,14 +425,13 @@ __global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
                 for (int j = 0; j < kIpt; ++j) {
                     const uint64_t f = base + expand_slot<kIpt>(j);
                     if (kGuard && f >= hi) continue;
-                    const uint64_t t = apply_gensel(st[j], sel);
                     uint32_t r;
                     if constexpr (!Incr) {
-                        r = perm_rank_t<N>(t);
+                        r = perm_rank_t<N>(apply_gensel(st[j], gsel[g]));
                     } else if constexpr (M <= N - 2) {
-                        r = rank_prefix<N, M>(t) + suf[j][M - 2];
+                        r = rank_prefix_from<N, M>(sk[j], gsh + (uint32_t)g * N) + suf[j][M - 2];
                     } else {
-                        r = rank_prefix<N, M>(t);
+                        r = rank_prefix_from<N, M>(sk[j], gsh + (uint32_t)g * N);
                     }
                     o[f] = r;
 #pragma unroll
