@@ -104,7 +104,8 @@ __host__ __device__ __forceinline__ R perm_rank_t(uint64_t key) {
 #pragma unroll
         for (int i = 1; i < N - 1; ++i) {
             const uint32_t v = (uint32_t)(key >> (4 * (N - 1 - i))) & 15u;
-            const uint32_t c = (uint32_t)__builtin_popcount(unused & ((1u << v) - 1u));
+            // unused values below v: the low v bits of the set, one extract
+            const uint32_t c = (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(unused, 0u, v));
             if (i <= kHi) {
                 hi = mad24<R>(hi, (R)(N - i), (R)c);
             } else {

@@ -292,13 +292,15 @@ __device__ __forceinline__ uint32_t times_top_fact(uint32_t v) {
     return mad24<uint32_t>(v, f >> s, 0u) << s;
 }
 
-// The same for t = s.g read straight from the parent s: entry i of t is
-// the nibble of s at bit sh[i] (sh uniform across the wave).
+// Entry i of the candidate t = s.g is the nibble of the parent s at bit
+// sh[i] (sh is the generator's row of shifts, the same across the wave).
 __device__ __forceinline__ uint32_t nibble_at(uint32_t lo, uint32_t hi, uint32_t sh) {
     // sh is uniform: one select of the half, one bit-field extract
     return __builtin_amdgcn_ubfe(sh < 32u ? lo : hi, sh & 31u, 4u);
 }
 
+// sum of c_i(t) (N-1-i)! over the positions i < min(M, N-1) of t = s.g,
+// reading t's entries from s through the shifts sh
 template <int N, int M>
 __device__ __forceinline__ uint32_t rank_prefix_from(uint64_t s, const uint32_t *__restrict__ sh) {
     constexpr int kEnd = M < N - 1 ? M : N - 1;
@@ -310,25 +312,7 @@ __device__ __forceinline__ uint32_t rank_prefix_from(uint64_t s, const uint32_t 
 #pragma unroll
     for (int i = 1; i < kEnd; ++i) {
         const uint32_t v = nibble_at(lo, hi, sh[i]);
-        const uint32_t c = (uint32_t)__builtin_popcount(unused & ((1u << v) - 1u));
-        acc = mad24<uint32_t>(c, fact_c(N - 1 - i), acc);
-        unused ^= 1u << v;
-    }
-    return acc;
-}
-
-// sum of c_i(t) (N-1-i)! over the positions i < min(M, N-1) of key t
-template <int N, int M>
-__device__ __forceinline__ uint32_t rank_prefix(uint64_t t) {
-    constexpr int kEnd = M < N - 1 ? M : N - 1;
-    uint32_t unused = (1u << N) - 1u;
-    const uint32_t v0 = (uint32_t)(t >> (4 * (N - 1))) & 15u;
-    uint32_t acc = times_top_fact<N>(v0);
-    unused ^= 1u << v0;
-#pragma unroll
-    for (int i = 1; i < kEnd; ++i) {
-        const uint32_t v = (uint32_t)(t >> (4 * (N - 1 - i))) & 15u;
-        const uint32_t c = (uint32_t)__builtin_popcount(unused & ((1u << v) - 1u));
+        const uint32_t c = (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(unused, 0u, v));
         acc = mad24<uint32_t>(c, fact_c(N - 1 - i), acc);
         unused ^= 1u << v;
     }
@@ -346,7 +330,7 @@ __device__ __forceinline__ void rank_suffixes(uint64_t s, uint32_t *dst) {
 #pragma unroll
         for (int i = 1; i < N - 1; ++i) {
             const uint32_t v = (uint32_t)(s >> (4 * (N - 1 - i))) & 15u;
-            c[i] = (uint32_t)__builtin_popcount(unused & ((1u << v) - 1u));
+            c[i] = (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(unused, 0u, v));
             unused ^= 1u << v;
         }
         uint32_t acc = 0;
@@ -493,6 +477,16 @@ __global__ void clear_kernel(unsigned long long *__restrict__ a, uint32_t na,
 #define CG_SORT_WPE 6
 #endif
 #define CG_SORT_ATTR __attribute__((amdgpu_waves_per_eu(CG_SORT_WPE)))
+// The digit (k >> shift) & dmask, dmask = 2^width - 1: one bit-field
+// extract for 32-bit keys (their digits never cross bit 32).
+template <class K>
+__device__ __forceinline__ uint32_t digit_of(K k, int shift, uint32_t dmask, uint32_t width) {
+    if constexpr (sizeof(K) == 4)
+        return __builtin_amdgcn_ubfe((uint32_t)k, (uint32_t)shift, width);
+    else
+        return (uint32_t)(k >> shift) & dmask;
+}
+
 // Lookback = true: tiles take tickets and chain their digit offsets by
 // decoupled look-back. Lookback = false: tile = block index and each
 // tile's digit offsets come precomputed in tile_off (reduce-then-scan).
@@ -514,8 +508,12 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
     static_assert(kIpt % 2 == 0 && kBuf * kSplit == kTileK, "two halves per register, whole rounds");
     __shared__ __align__(16) K s_keys[kBuf];
     __shared__ uint32_t s_cnt[kWv][kRadix];
-    __shared__ uint64_t s_gstart[kRadix];
-    __shared__ uint32_t s_lstart[kRadix];
+    // per digit: its output start minus its start in the tile-sorted order,
+    // one LDS read per key in the scatter; 64-bit keys keep the two starts
+    // apart (folded, that pass spills a register)
+    constexpr bool kFold = sizeof(K) == 4;
+    __shared__ uint64_t s_gdelta[kRadix];
+    __shared__ uint32_t s_lstart[kFold ? 1 : kRadix];
     __shared__ uint32_t s_scan[kWv];
     __shared__ uint32_t s_tile;
 
@@ -526,6 +524,7 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
     static_assert(kIpt % kRows == 0, "rows per group divide the rows per thread");
 
     constexpr bool kPersist = Lookback && (sizeof(K) == 4 ? CG_SORT_PERSIST32 : CG_SORT_PERSIST64);
+    const uint32_t dwidth = (uint32_t)__builtin_popcount(dmask);
     if (Lookback && threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     // With look-back the blocks are persistent: each takes tiles in ticket
     // order until the tickets run out (every block ends on a ticket past the
@@ -578,7 +577,7 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
     for (int j0 = 0; j0 < kIpt; j0 += kRows) {
         uint32_t d[kRows];
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) d[r] = (uint32_t)(key[j0 + r] >> shift) & dmask;
+        for (int r = 0; r < kRows; ++r) d[r] = digit_of(key[j0 + r], shift, dmask, dwidth);
 #if CG_SORT_HALF_MASK
         // a lane sets (and later clears) only its half-wave's 32-bit word
 #pragma unroll
@@ -658,16 +657,19 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
                                                                                       epoch, err);
                 lb_store(my, lb_word(epoch, kFlagInclusive, excl + pub));
             }
-            s_gstart[d] = (uint64_t)digit_base[d] + excl;
+            s_gdelta[d] = (uint64_t)digit_base[d] + excl;
         } else {
-            s_gstart[d] = tile_off[(uint64_t)tile * kRadix + d];
+            s_gdelta[d] = tile_off[(uint64_t)tile * kRadix + d];
         }
     }
     {
         uint32_t tot;
         const uint32_t lstart = block_excl_scan<kWv>(run, s_scan, &tot);  // every thread takes part
         if (tid < (uint32_t)kRadix) {
-            s_lstart[tid] = lstart;
+            if constexpr (kFold)
+                s_gdelta[tid] -= lstart;  // may wrap below zero; the sum below does not
+            else
+                s_lstart[tid] = lstart;
             // each wave's slot for this digit in the tile-sorted order
 #pragma unroll
             for (int w = 0; w < kWv; ++w) s_cnt[w][tid] += lstart;
@@ -682,8 +684,8 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
         // of the ranking would keep 32 of them live across the look-back
         K k0 = key[j], k1 = key[j + 1];
         __asm__ volatile("" : "+v"(k0), "+v"(k1));
-        const uint32_t d0 = (uint32_t)(k0 >> shift) & dmask;
-        const uint32_t d1 = (uint32_t)(k1 >> shift) & dmask;
+        const uint32_t d0 = digit_of(k0, shift, dmask, dwidth);
+        const uint32_t d1 = digit_of(k1, shift, dmask, dwidth);
         const uint32_t p0 = s_cnt[wave][d0] + (rank2[j >> 1] & 0xFFFFu);
         const uint32_t p1 = s_cnt[wave][d1] + (rank2[j >> 1] >> 16);
         rank2[j >> 1] = p0 | (p1 << 16);
@@ -705,8 +707,8 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
         const uint32_t cnt = nvalid - lo < (uint32_t)kBuf ? nvalid - lo : (uint32_t)kBuf;
         for (uint32_t i = tid; i < cnt; i += kBlk) {
             const K k = s_keys[i];
-            const uint32_t d = (uint32_t)(k >> shift) & dmask;
-            const uint64_t gpos = s_gstart[d] + (lo + i - s_lstart[d]);
+            const uint32_t d = digit_of(k, shift, dmask, dwidth);
+            const uint64_t gpos = kFold ? s_gdelta[d] + (lo + i) : s_gdelta[d] + (lo + i - s_lstart[d]);
             if (gpos < total)
                 out[gpos] = k;
             else
