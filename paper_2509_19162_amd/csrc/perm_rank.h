@@ -67,6 +67,16 @@ __host__ __device__ __forceinline__ R mad24(R a, R b, R c) {
     return a * b + c;
 }
 
+// The low v bits of x (v < 32): on the device one bit-field extract, where
+// the plain expression costs a mask build and an AND.
+__host__ __device__ __forceinline__ uint32_t low_bits(uint32_t x, uint32_t v) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_ubfe(x, 0u, v);
+#else
+    return x & ((1u << v) - 1u);
+#endif
+}
+
 // Last position whose Horner prefix N (N-1) ... (N-i) stays below 2^24.
 template <int N>
 constexpr int rank_split() {
@@ -104,8 +114,7 @@ __host__ __device__ __forceinline__ R perm_rank_t(uint64_t key) {
 #pragma unroll
         for (int i = 1; i < N - 1; ++i) {
             const uint32_t v = (uint32_t)(key >> (4 * (N - 1 - i))) & 15u;
-            // unused values below v: the low v bits of the set, one extract
-            const uint32_t c = (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(unused, 0u, v));
+            const uint32_t c = (uint32_t)__builtin_popcount(low_bits(unused, v));
             if (i <= kHi) {
                 hi = mad24<R>(hi, (R)(N - i), (R)c);
             } else {

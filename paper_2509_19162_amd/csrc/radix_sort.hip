@@ -312,7 +312,7 @@ __device__ __forceinline__ uint32_t rank_prefix_from(uint64_t s, const uint32_t 
 #pragma unroll
     for (int i = 1; i < kEnd; ++i) {
         const uint32_t v = nibble_at(lo, hi, sh[i]);
-        const uint32_t c = (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(unused, 0u, v));
+        const uint32_t c = (uint32_t)__builtin_popcount(low_bits(unused, v));
         acc = mad24<uint32_t>(c, fact_c(N - 1 - i), acc);
         unused ^= 1u << v;
     }
@@ -330,7 +330,7 @@ __device__ __forceinline__ void rank_suffixes(uint64_t s, uint32_t *dst) {
 #pragma unroll
         for (int i = 1; i < N - 1; ++i) {
             const uint32_t v = (uint32_t)(s >> (4 * (N - 1 - i))) & 15u;
-            c[i] = (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(unused, 0u, v));
+            c[i] = (uint32_t)__builtin_popcount(low_bits(unused, v));
             unused ^= 1u << v;
         }
         uint32_t acc = 0;
