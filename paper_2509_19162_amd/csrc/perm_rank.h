@@ -127,27 +127,56 @@ __host__ __device__ __forceinline__ R perm_rank_t(uint64_t key) {
     }
 }
 
+// The inverse with n fixed at compile time (n <= 16). The unused values,
+// smallest first, are kept as a list of nibbles in two 32-bit words (lo:
+// entries 0-7, hi: entries 8-15), so every step is 32-bit work: read entry
+// c, then move the entries after it down one nibble, from hi into lo where
+// the list still reaches into hi (decided at compile time per position).
 template <int N, class R = uint32_t>
 __host__ __device__ __forceinline__ uint64_t perm_unrank_t(R rank) {
+    static_assert(N <= 16, "16 nibbles at most");
     uint32_t c[N > 0 ? N : 1];
 #pragma unroll
     for (int i = N - 1; i >= 0; --i) {
         c[i] = (uint32_t)(rank % (R)(N - i));
         rank /= (R)(N - i);
     }
-    uint64_t avail = 0;
+    uint32_t lo = 0, hi = 0;
 #pragma unroll
-    for (int j = 0; j < N; ++j) avail |= (uint64_t)j << (4 * j);
-    uint64_t key = 0;
+    for (int j = 0; j < N; ++j) {
+        if (j < 8)
+            lo |= (uint32_t)j << (4 * j);
+        else
+            hi |= (uint32_t)j << (4 * (j - 8));
+    }
+    uint32_t klo = 0, khi = 0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        const uint32_t sh = 4 * c[i];
-        const uint64_t v = (avail >> sh) & 15u;
-        const uint64_t low = avail & ((1ull << sh) - 1ull);
-        avail = low | ((avail >> (sh + 4)) << sh);
-        key |= v << (4 * (N - 1 - i));
+        const uint32_t sh = 4 * c[i];  // c[i] < N - i
+        uint32_t v;
+        if (N - i > 8) {
+            const bool in_hi = sh >= 32u;
+            const uint32_t s5 = sh & 31u;
+            v = ((in_hi ? hi : lo) >> s5) & 15u;
+            const uint32_t keep = (1u << s5) - 1u;  // the entries before c stay
+            const uint32_t lo_dn = (lo >> 4) | (hi << 28);
+            const uint32_t hi_dn = hi >> 4;
+            const uint32_t lo_rm = (lo & keep) | (lo_dn & ~keep);
+            const uint32_t hi_rm = (hi & keep) | (hi_dn & ~keep);
+            lo = in_hi ? lo : lo_rm;
+            hi = in_hi ? hi_rm : hi_dn;
+        } else {  // at most 8 entries left, all in lo
+            v = (lo >> sh) & 15u;
+            const uint32_t keep = (1u << sh) - 1u;
+            lo = (lo & keep) | ((lo >> 4) & ~keep);
+        }
+        const int pos = 4 * (N - 1 - i);
+        if (pos >= 32)
+            khi |= v << (pos - 32);
+        else
+            klo |= v << pos;
     }
-    return key;
+    return ((uint64_t)khi << 32) | klo;
 }
 
 // Calls f(std::integral_constant<int, N>{}) for the runtime n in 1..12.
