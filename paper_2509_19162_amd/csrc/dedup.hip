@@ -42,6 +42,10 @@ constexpr int kWaves = kBlock / kWave;
 #endif
 constexpr int kIpt = CG_DEDUP_IPT;
 constexpr int kTile = kBlock * kIpt;  // 4096 candidates per dedup tile by default
+#ifndef CG_GATHER_TILES
+#define CG_GATHER_TILES 4
+#endif
+constexpr int kGatherTiles = CG_GATHER_TILES;  // dedup tiles per gather block
 constexpr int kRefIpt = 4;            // reference keys per thread loaded with the tile
 #ifndef CG_DEDUP_LOCKSTEP
 #define CG_DEDUP_LOCKSTEP 1  // the tile's first references searched in lockstep
@@ -328,27 +332,56 @@ __global__ __launch_bounds__(kScanBlock) void count_scan_kernel(
 }
 
 // Phase 3: move each tile's survivors to their final place (and, for
-// ranked candidates, their ranks to rank_out when it is given).
+// ranked candidates, their ranks to rank_out when it is given). For ranked
+// candidates a block takes kGatherTiles consecutive tiles: a tile keeps a
+// few hundred survivors in the large layers, each is unranked on the way,
+// and one block per tile would spend most of its life waiting on its one
+// load. In each round a thread first loads its survivor of every tile of
+// the block, then converts and stores them. Packed survivors only move, and
+// there one tile per block measured faster.
+template <class P>
+constexpr int gather_tiles() {
+    return sizeof(typename P::K) == 4 ? kGatherTiles : 1;
+}
+
 template <class P>
 __global__ __launch_bounds__(kBlock) void gather_kernel(P pol, const typename P::K *__restrict__ tmp,
                                                         const uint32_t *__restrict__ cnt,
-                                                        const uint64_t *__restrict__ off,
+                                                        const uint64_t *__restrict__ off, uint32_t ntiles,
                                                         uint64_t *__restrict__ out, uint64_t out_cap,
                                                         uint32_t *__restrict__ rank_out,
                                                         uint32_t *__restrict__ err) {
-    const uint32_t tile = blockIdx.x;
-    const uint32_t c = cnt[tile];
-    const uint64_t o = off[tile];
-    const uint64_t base = (uint64_t)tile * kTile;
-    for (uint32_t i = threadIdx.x; i < c; i += kBlock) {
-        if (o + i < out_cap) {
-            const typename P::K v = tmp[base + i];
-            out[o + i] = pol.to_layer(v);
-            if constexpr (sizeof(typename P::K) == 4)
-                if (rank_out) rank_out[o + i] = v;
+    using K = typename P::K;
+    constexpr int kT = gather_tiles<P>();
+    const uint32_t t0 = blockIdx.x * (uint32_t)kT;
+    const uint32_t tid = threadIdx.x;
+    auto put = [&](uint64_t dst, K v) {
+        if (dst < out_cap) {
+            out[dst] = pol.to_layer(v);
+            if constexpr (sizeof(K) == 4)
+                if (rank_out) rank_out[dst] = v;
         } else {
             atomicOr(err, 4u);  // more survivors than the output holds
         }
+    };
+    uint32_t c[kT];
+    uint64_t o[kT];
+    uint32_t cmax = 0;
+#pragma unroll
+    for (int t = 0; t < kT; ++t) {
+        const bool in = t0 + t < ntiles;
+        c[t] = in ? cnt[t0 + t] : 0u;
+        o[t] = in ? off[t0 + t] : 0ull;
+        cmax = c[t] > cmax ? c[t] : cmax;
+    }
+    for (uint32_t i = tid; i < cmax; i += kBlock) {
+        K v[kT];
+#pragma unroll
+        for (int t = 0; t < kT; ++t)
+            if (i < c[t]) v[t] = tmp[(uint64_t)(t0 + t) * kTile + i];
+#pragma unroll
+        for (int t = 0; t < kT; ++t)
+            if (i < c[t]) put(o[t] + i, v[t]);
     }
 }
 
@@ -419,9 +452,11 @@ void dedup_gather_impl(P pol, const typename P::K *tmp, uint64_t *out, uint64_t 
                        uint32_t *rank_out = nullptr) {
     if (!w.dedup_tiles) return;
     if (w.prof) w.prof->begin(K_DEDUP);
-    hipLaunchKernelGGL(gather_kernel<P>, dim3(w.dedup_tiles), dim3(kBlock), 0, w.stream, pol, tmp,
-                       w.tile_cnt.as<const uint32_t>(), w.tile_off.as<const uint64_t>(), out, out_cap,
-                       rank_out, w.err());
+    const uint32_t ntiles = (uint32_t)w.dedup_tiles;
+    constexpr uint32_t tpb = (uint32_t)gather_tiles<P>();
+    hipLaunchKernelGGL(gather_kernel<P>, dim3((ntiles + tpb - 1) / tpb), dim3(kBlock), 0,
+                       w.stream, pol, tmp, w.tile_cnt.as<const uint32_t>(), w.tile_off.as<const uint64_t>(), ntiles,
+                       out, out_cap, rank_out, w.err());
     CG_HIP(hipGetLastError());
     if (w.prof) w.prof->end(K_DEDUP, 0, 0);
 }
