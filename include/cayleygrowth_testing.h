@@ -84,7 +84,8 @@ int cg_test_layer_step(int n, const uint8_t *h_gens, int k,
 
 /*
  * Lexicographic rank of permutation keys (n <= 12): h_ranks[i] = the index
- * of the permutation in lexicographic order of S_n. on_device = 1 runs the
+ * of the permutation in lexicographic order of S_n, computed by the rank of
+ * the growth kernels (n fixed at compile time). on_device = 1 runs the
  * device code (host buffers are staged), 0 the same code on the host.
  * cg_test_unrank is the inverse (h_ranks < n! required).
  */

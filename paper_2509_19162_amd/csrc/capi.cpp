@@ -324,14 +324,19 @@ __global__ __launch_bounds__(256) void copy_kernel(const uint4 *__restrict__ src
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
 }
 
-__global__ void rank_kernel(int n, const uint64_t *k, uint64_t count, uint32_t *r) {
+// the rank and unrank of the growth kernels (n fixed at compile time)
+extern "C++" {
+template <int N>
+__global__ void rank_kernel(const uint64_t *k, uint64_t count, uint32_t *r) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) r[i] = cg::perm_rank(k[i], n);
+    if (i < count) r[i] = cg::perm_rank_t<N>(k[i]);
 }
 
-__global__ void unrank_kernel(int n, const uint32_t *r, uint64_t count, uint64_t *k) {
+template <int N>
+__global__ void unrank_kernel(const uint32_t *r, uint64_t count, uint64_t *k) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) k[i] = cg::perm_unrank(r[i], n);
+    if (i < count) k[i] = cg::perm_unrank_t<N>(r[i]);
+}
 }
 
 // v_perm_b32: byte j of the result selects from the 8-byte {s0:s1} (s1 the
@@ -361,7 +366,9 @@ int cg_test_rank(int n, const uint64_t *h_keys, uint64_t count, uint32_t *h_rank
         if (n < 1 || n > cg::kRankMaxN || (count && (!h_keys || !h_ranks)))
             throw cg::Error(CG_E_INVAL, "bad rank arguments");
         if (!on_device) {
-            for (uint64_t i = 0; i < count; ++i) h_ranks[i] = cg::perm_rank(h_keys[i], n);
+            cg::with_rank_n(n, [&](auto NN) {
+                for (uint64_t i = 0; i < count; ++i) h_ranks[i] = cg::perm_rank_t<decltype(NN)::value>(h_keys[i]);
+            });
             return CG_OK;
         }
         if (!count) return CG_OK;
@@ -371,8 +378,10 @@ int cg_test_rank(int n, const uint64_t *h_keys, uint64_t count, uint32_t *h_rank
         a.ensure(count * 8);
         b.ensure(count * 4);
         CG_HIP(hipMemcpyAsync(a.p, h_keys, count * 8, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(rank_kernel, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, s, n,
-                           a.as<uint64_t>(), count, b.as<uint32_t>());
+        cg::with_rank_n(n, [&](auto NN) {
+            hipLaunchKernelGGL(rank_kernel<decltype(NN)::value>, dim3((uint32_t)((count + 255) / 256)), dim3(256),
+                               0, s, a.as<uint64_t>(), count, b.as<uint32_t>());
+        });
         CG_HIP(hipGetLastError());
         CG_HIP(hipMemcpyAsync(h_ranks, b.p, count * 4, hipMemcpyDeviceToHost, s));
         CG_HIP(hipStreamSynchronize(s));
@@ -390,7 +399,9 @@ int cg_test_unrank(int n, const uint32_t *h_ranks, uint64_t count, uint64_t *h_k
         for (uint64_t i = 0; i < count; ++i)
             if (h_ranks[i] >= fact) throw cg::Error(CG_E_INVAL, "rank out of range");
         if (!on_device) {
-            for (uint64_t i = 0; i < count; ++i) h_keys[i] = cg::perm_unrank(h_ranks[i], n);
+            cg::with_rank_n(n, [&](auto NN) {
+                for (uint64_t i = 0; i < count; ++i) h_keys[i] = cg::perm_unrank_t<decltype(NN)::value>(h_ranks[i]);
+            });
             return CG_OK;
         }
         if (!count) return CG_OK;
@@ -400,8 +411,10 @@ int cg_test_unrank(int n, const uint32_t *h_ranks, uint64_t count, uint64_t *h_k
         a.ensure(count * 4);
         b.ensure(count * 8);
         CG_HIP(hipMemcpyAsync(a.p, h_ranks, count * 4, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(unrank_kernel, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, s, n,
-                           a.as<uint32_t>(), count, b.as<uint64_t>());
+        cg::with_rank_n(n, [&](auto NN) {
+            hipLaunchKernelGGL(unrank_kernel<decltype(NN)::value>, dim3((uint32_t)((count + 255) / 256)),
+                               dim3(256), 0, s, a.as<uint32_t>(), count, b.as<uint64_t>());
+        });
         CG_HIP(hipGetLastError());
         CG_HIP(hipMemcpyAsync(h_keys, b.p, count * 8, hipMemcpyDeviceToHost, s));
         CG_HIP(hipStreamSynchronize(s));

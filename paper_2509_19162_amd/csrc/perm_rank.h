@@ -27,27 +27,6 @@ __host__ __device__ __forceinline__ uint32_t perm_rank(uint64_t key, int n) {
     return rank;
 }
 
-__host__ __device__ __forceinline__ uint64_t perm_unrank(uint32_t rank, int n) {
-    // mixed-radix digits, last position first
-    uint32_t c[16];
-    for (int i = n - 1; i >= 0; --i) {
-        const uint32_t radix = (uint32_t)(n - i);
-        c[i] = rank % radix;
-        rank /= radix;
-    }
-    uint64_t avail = 0;  // nibble j holds the j-th smallest unused value
-    for (int j = 0; j < n; ++j) avail |= (uint64_t)j << (4 * j);
-    uint64_t key = 0;
-    for (int i = 0; i < n; ++i) {
-        const uint32_t sh = 4 * c[i];
-        const uint64_t v = (avail >> sh) & 15u;
-        const uint64_t low = sh ? (avail & ((1ull << sh) - 1ull)) : 0ull;
-        avail = low | ((avail >> (sh + 4)) << sh);
-        key |= v << (4 * (n - 1 - i));
-    }
-    return key;
-}
-
 // a * b + c for a, b < 2^24 (both factors of every use below are): a 24-bit
 // multiply-add for 32-bit ranks, a plain one for 64-bit ranks (the product
 // may exceed 32 bits there). On the device b goes through a scalar

@@ -19,7 +19,7 @@ def pack(n, rows):
     return np.bitwise_or.reduce(rows << shifts, axis=1)
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 7])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7, 9])
 def test_rank_is_lexicographic_index(n):
     perms = list(itertools.permutations(range(n)))  # lexicographic order
     keys = np.ascontiguousarray(pack(n, perms))
@@ -34,7 +34,7 @@ def test_rank_is_lexicographic_index(n):
     assert rc == 0 and np.array_equal(back, keys)
 
 
-@pytest.mark.parametrize("n", [10, 12])
+@pytest.mark.parametrize("n", [10, 11, 12])
 def test_rank_sampled_large_n(n):
     rng = np.random.default_rng(n)
     perms = [list(map(int, rng.permutation(n))) for _ in range(500)]
@@ -48,6 +48,14 @@ def test_rank_sampled_large_n(n):
         assert code == int(r)
     order = np.argsort(keys, kind="stable")
     assert np.all(np.diff(ranks[order].astype(np.int64)) > 0)  # order preserved
+    # unrank inverts it; rank 0 is the identity and n! - 1 the reversal
+    rs = np.ascontiguousarray(np.concatenate([ranks, [0, math.factorial(n) - 1]]).astype(np.uint32))
+    back = np.zeros(len(rs), dtype=np.uint64)
+    assert N.lib().cg_test_unrank(n, rs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), len(rs),
+                                  back.ctypes.data_as(N.u64p), 0, None) == 0
+    assert np.array_equal(back[:-2], keys)
+    assert int(back[-2]) == int(pack(n, [list(range(n))])[0])
+    assert int(back[-1]) == int(pack(n, [list(range(n))[::-1]])[0])
 
 
 def test_rank_rejects_bad_input():
