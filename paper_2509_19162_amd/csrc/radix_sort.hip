@@ -95,6 +95,21 @@ constexpr int kRows = CG_SORT_ROWS;  // rows ranked per LDS round trip
 #ifndef CG_SORT_PERSIST64
 #define CG_SORT_PERSIST64 1
 #endif
+// Streaming (non-temporal) key loads and scatter stores, per key width:
+// for 64-bit keys they cut S_16 LRX sort passes by 6%; for 32-bit ranks
+// the streaming stores cost 13% and the loads 1%, so those stay plain.
+#ifndef CG_SORT_NT_LOAD32
+#define CG_SORT_NT_LOAD32 0
+#endif
+#ifndef CG_SORT_NT_STORE32
+#define CG_SORT_NT_STORE32 0
+#endif
+#ifndef CG_SORT_NT_LOAD64
+#define CG_SORT_NT_LOAD64 1
+#endif
+#ifndef CG_SORT_NT_STORE64
+#define CG_SORT_NT_STORE64 1
+#endif
 #ifndef CG_SORT_HALF_MASK
 #define CG_SORT_HALF_MASK 1  // peer masks set and cleared by 32-bit halves
 #endif
@@ -112,7 +127,12 @@ struct ArraySrcT {
     struct Tile {
         const K *p;
         uint32_t n;
-        __device__ __forceinline__ K get(uint32_t i) const { return p[i]; }
+        __device__ __forceinline__ K get(uint32_t i) const {
+            if constexpr (sizeof(K) == 4 ? CG_SORT_NT_LOAD32 : CG_SORT_NT_LOAD64)
+                return __builtin_nontemporal_load(p + i);
+            else
+                return p[i];
+        }
     };
     static constexpr uint64_t kLen = TileOf<K>::tile;
     __device__ __forceinline__ Tile tile(uint32_t t) const {
@@ -709,10 +729,14 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
             const K k = s_keys[i];
             const uint32_t d = digit_of(k, shift, dmask, dwidth);
             const uint64_t gpos = kFold ? s_gdelta[d] + (lo + i) : s_gdelta[d] + (lo + i - s_lstart[d]);
-            if (gpos < total)
-                out[gpos] = k;
-            else
+            if (gpos < total) {
+                if constexpr (sizeof(K) == 4 ? CG_SORT_NT_STORE32 : CG_SORT_NT_STORE64)
+                    __builtin_nontemporal_store(k, out + gpos);
+                else
+                    out[gpos] = k;
+            } else {
                 atomicOr(err, 2u);  // inconsistent offsets: never write out of bounds
+            }
         }
     }
     if constexpr (!kPersist) break;
