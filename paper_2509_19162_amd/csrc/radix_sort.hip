@@ -830,8 +830,11 @@ PassDesc make_passes(int bit_lo, int bit_hi) {
     return pd;
 }
 
+#ifndef CG_HIST_GRID_CAP
+#define CG_HIST_GRID_CAP 8192  // blocks of the one-read histogram (grid-stride over tiles)
+#endif
 uint32_t hist_grid(uint32_t ntiles) {
-    const uint32_t cap = 2048;
+    const uint32_t cap = CG_HIST_GRID_CAP;
     return ntiles < cap ? (ntiles ? ntiles : 1) : cap;
 }
 
