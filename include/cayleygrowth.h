@@ -213,6 +213,36 @@ typedef struct cg_batch_opts {
 int cg_growth_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results,
                     const cg_batch_opts_t *opts);
 
+/*
+ * cg_growth_batch_noalloc -- cg_growth_batch for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). It runs every job in the
+ * small-job engine (one workgroup per job, one launch) and keeps all its
+ * device buffers in one static array of the library (64 MiB, held by each
+ * GPU the library runs on until the process ends): it calls no hipMalloc,
+ * hipFree, event or stream creation. Results equal cg_growth_batch's bit
+ * for bit.
+ *   jobs, results  host arrays as for cg_growth_batch (inputs borrowed for
+ *                  the call; results[i].layer_sizes caller-owned, holding
+ *                  jobs[i].max_layers entries)
+ *   stream         hipStream_t to run on, or NULL (the null stream); the
+ *                  call synchronises it before returning
+ * Limits (CG_E_INVAL beyond them, nothing launched): at most 4096 jobs;
+ * every job with n <= 10, a permutation start and at most 128 distinct
+ * generators (CG_ALLOW_DIRECTED allowed; no CG_KEEP_ALL_LAYERS or
+ * layers_out); at most 32768 distinct generator rows and 2^21 recorded
+ * layer sizes (sum over jobs of min(max_layers, n!)) in all. A job with a
+ * bad generator row gets CG_E_INVAL in its own result. device_ms is the
+ * host-timed span from the launch to the end of the read-back.
+ * The array is shared by every call on one GPU and keeps the last call's
+ * contents (the call clears what must start at zero). Calls that overlap
+ * on one GPU would race on it; within this process they are serialised by
+ * a lock per device.
+ * Returns CG_OK when every job ran (see each results[i].status) or a
+ * negative error for the whole call.
+ */
+int cg_growth_batch_noalloc(int n_jobs, const cg_job_t *jobs, cg_result_t *results, void *stream);
+
 /* ---- serving: a request queue with continuous batching ------------------ */
 typedef struct cg_queue cg_queue_t;
 

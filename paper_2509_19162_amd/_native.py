@@ -127,6 +127,8 @@ SIGNATURES = [
     ("cg_engine_destroy", None, [ctypes.c_void_p]),
     ("cg_growth_batch", ctypes.c_int,
      [ctypes.c_int, ctypes.POINTER(CgJob), ctypes.POINTER(CgResult), ctypes.POINTER(CgBatchOpts)]),
+    ("cg_growth_batch_noalloc", ctypes.c_int,
+     [ctypes.c_int, ctypes.POINTER(CgJob), ctypes.POINTER(CgResult), ctypes.c_void_p]),
     ("cg_queue_create", ctypes.c_void_p, [ctypes.POINTER(CgQueueOpts)]),
     ("cg_queue_submit", ctypes.c_int,
      [ctypes.c_void_p, ctypes.POINTER(CgJob), ctypes.POINTER(CgResult), u64p]),

@@ -226,6 +226,29 @@ def growth_batch(jobs, max_layers: int = 256, max_active: int = 0, budget_bytes:
     return out
 
 
+def growth_batch_noalloc(jobs, max_layers: int = 256, stream=None,
+                         allow_directed: bool = False) -> List[GrowthResult]:
+    """``cg_growth_batch_noalloc``: the jobs of ``growth_batch`` (each with
+    n <= 10) run without any device allocation, on the library's static
+    device array. Same job tuple forms as ``growth_batch``."""
+    holders = []
+    for j in jobs:
+        n, gens = j[0], j[1]
+        mf = j[2] if len(j) > 2 else None
+        ml = j[3] if len(j) > 3 and j[3] else max_layers
+        holders.append(_JobHolder(n, gens, ml, mf, N.CG_ALLOW_DIRECTED if allow_directed else 0, None, 0))
+    ja = (N.CgJob * len(holders))(*[h.job for h in holders])
+    ra = (N.CgResult * len(holders))()
+    for i, h in enumerate(holders):
+        ra[i].layer_sizes = h.sizes.ctypes.data_as(N.u64p)
+    _check(N.lib().cg_growth_batch_noalloc(len(holders), ja, ra, _stream_handle(stream)))
+    out = []
+    for i, h in enumerate(holders):
+        h.res = ra[i]
+        out.append(h.result())
+    return out
+
+
 _WORKSPACE = None  # keeps the caller's tensor alive while the library uses it
 
 

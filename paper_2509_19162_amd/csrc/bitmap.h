@@ -71,6 +71,16 @@ private:
 // candidates on it (cached per device and n class for the process).
 WgTuning tune_wg(std::vector<WgItem> &sample, hipStream_t s);
 
+// cg_growth_batch_noalloc: the small-job engine on the library's static
+// device array (no allocation). Limits per call: jobs, distinct generator
+// rows in all, and layer-size entries in all (sum of min(max_layers, n!)).
+constexpr uint32_t kNoAllocMaxJobs = 4096;
+constexpr uint32_t kNoAllocMaxGens = 32768;
+constexpr uint64_t kNoAllocMaxSizes = 1ull << 21;
+void run_batch_noalloc(int n_jobs, const cg_job_t *jobs, cg_result_t *results, hipStream_t stream);
+// The current device's address of that array (taken once per device).
+void *noalloc_scratch(int dev);
+
 // The bitmask engine: whole-device growth of one job (n <= 14, start a
 // permutation). Fills res like Engine::run. Layers are not exported.
 void run_bitmask(const JobSpec &spec, cg_result_t *res, hipStream_t s);

@@ -7,6 +7,7 @@
 // "every earlier layer", so no closure under inverses is assumed.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -16,6 +17,16 @@
 #include "expand_device.h"
 #include "internal.h"
 #include "perm_rank.h"
+
+// Device memory of cg_growth_batch_noalloc: every buffer its launch needs
+// beyond the caller's inputs and outputs (job table, generator table,
+// layer-size and outcome staging, the job-queue tickets, the per-workgroup
+// bitmap slots of n = 9, 10 jobs). Each GPU the library runs on holds its
+// own copy until the process ends. Host code never uses this name as an
+// address: it takes the device address once per device from
+// hipGetSymbolAddress (cg::noalloc_scratch).
+constexpr size_t kNoAllocScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 namespace cg {
 
@@ -153,10 +164,15 @@ __device__ __forceinline__ void wg_run(const WgJobDev &J, const GenSel *__restri
 }
 
 // One persistent launch for a whole batch: each workgroup takes the next
-// job from the queue (jobs are ordered by decreasing size) and runs it to
+// job from a queue (jobs are ordered by decreasing size) and runs it to
 // completion. Jobs with n >= 9 use the workgroup's slot of `gbits`
-// (3 * slot_words words, checked by the host to hold their bitmaps).
+// (3 * slot_words words, checked by the host to hold their bitmaps); only
+// workgroups below n_slot_blocks own a slot. Two queues: ticket[0] hands
+// out jobs [0, n_slot_jobs) to workgroups that own a slot, ticket[1] jobs
+// [n_slot_jobs, njobs) to every workgroup (the host puts a job with
+// n >= 9 there only when every workgroup owns a slot).
 __global__ __launch_bounds__(kWgMaxBlock) void wg_growth_kernel(const WgJobDev *__restrict__ jobs, uint32_t njobs,
+                                                                uint32_t n_slot_jobs, uint32_t n_slot_blocks,
                                                                 const GenSel *__restrict__ gtab,
                                                                 uint64_t *__restrict__ sizes,
                                                                 WgOutDev *__restrict__ outs, uint32_t *ticket,
@@ -164,14 +180,27 @@ __global__ __launch_bounds__(kWgMaxBlock) void wg_growth_kernel(const WgJobDev *
     __shared__ uint32_t s_bits[3 * kWgLdsWords];
     __shared__ GenSel s_sel[kBitmapMaxK];
     __shared__ uint32_t s_acc, s_job;
-    uint32_t *slot = gbits ? gbits + (uint64_t)blockIdx.x * 3ull * slot_words : nullptr;
+    const bool has_slot = gbits && blockIdx.x < n_slot_blocks;
+    uint32_t *slot = has_slot ? gbits + (uint64_t)blockIdx.x * 3ull * slot_words : nullptr;
+    for (uint32_t q = has_slot ? 0u : 1u; q < 2u; ++q) {
+    const uint32_t q_lo = q ? n_slot_jobs : 0u, q_hi = q ? njobs : n_slot_jobs;
     for (;;) {
-        if (threadIdx.x == 0) s_job = atomicAdd(ticket, 1u);
+        if (threadIdx.x == 0) s_job = atomicAdd(ticket + q, 1u);
         __syncthreads();
-        const uint32_t j = s_job;
+        const uint32_t t = s_job;
         __syncthreads();
-        if (j >= njobs) break;
+        if (t >= q_hi - q_lo) break;
+        const uint32_t j = q_lo + t;
         const WgJobDev J = jobs[j];
+        if (J.n > kWgLdsN && !slot) {
+            // a host bookkeeping error: report it instead of touching memory
+            if (threadIdx.x == 0) {
+                outs[j].status = CG_E_DEVICE;
+                outs[j].num_layers = 0;
+                outs[j].expanded = 0;
+            }
+            continue;
+        }
         uint64_t *sz = sizes + J.sizes_off;
         uint32_t *l0 = s_bits, *l1 = s_bits + kWgLdsWords, *l2 = s_bits + 2 * kWgLdsWords;
         switch (J.n) {
@@ -191,6 +220,7 @@ __global__ __launch_bounds__(kWgMaxBlock) void wg_growth_kernel(const WgJobDev *
                 break;
         }
         __syncthreads();
+    }
     }
 }
 
@@ -348,41 +378,93 @@ WgRunner::~WgRunner() {
     for (DevBuf *b : {&jobs_, &gsel_, &sizes_, &outs_, &ws_, &ticket_}) b->release();
 }
 
-double WgRunner::run(std::vector<WgItem> &items, const WgTuning &t, double t_submit) {
+namespace {
+
+// Host tables of one small-job launch, jobs in launch order.
+struct WgTables {
+    std::vector<uint32_t> order;  // launch position -> item index
+    std::vector<WgJobDev> jobs;
+    std::vector<GenSel> gsel;
+    uint64_t sizes_total = 0;     // layer-size entries of all jobs
+    uint64_t slot_words = 0;      // words per bitmap of a device slot (0: no job needs one)
+    uint32_t n_slot_jobs = 0;     // slot_first: jobs [0, n_slot_jobs) have n >= 9
+    int n_max = 0;
+};
+
+// Largest jobs first (the queue then balances like longest-first); with
+// slot_first the jobs whose bitmaps need a device slot come before all
+// others. A job records at most min(max_layers, orbit) layer sizes: every
+// recorded layer holds at least one state of the orbit.
+WgTables wg_tables(const std::vector<WgItem> &items, bool slot_first) {
     const uint32_t nj = (uint32_t)items.size();
-    if (!nj) return 0.0;
-    if (t.block < 64 || t.block > kWgMaxBlock || t.block % kWave) throw Error(CG_E_INVAL, "bad workgroup size");
-    // largest jobs first: the queue then balances like longest-first
-    std::vector<uint32_t> order(nj);
-    for (uint32_t i = 0; i < nj; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+    WgTables T;
+    T.order.resize(nj);
+    for (uint32_t i = 0; i < nj; ++i) T.order[i] = i;
+    std::stable_sort(T.order.begin(), T.order.end(), [&](uint32_t a, uint32_t b) {
         const JobSpec &x = *items[a].spec, &y = *items[b].spec;
+        if (slot_first && (x.n > (int)kWgLdsN) != (y.n > (int)kWgLdsN)) return x.n > (int)kWgLdsN;
         const double cx = (double)factorial(x.n) * (x.k + 1), cy = (double)factorial(y.n) * (y.k + 1);
         return cx > cy;
     });
-    std::vector<WgJobDev> hj(nj);
-    std::vector<GenSel> hs;
-    uint64_t sizes_total = 0, slot_words = 0;
+    T.jobs.resize(nj);
     for (uint32_t i = 0; i < nj; ++i) {
-        const JobSpec &s = *items[order[i]].spec;
+        const JobSpec &s = *items[T.order[i]].spec;
         if (!wg_eligible(s)) throw Error(CG_E_INVAL, "job not eligible for the small-job engine");
-        WgJobDev &d = hj[i];
+        WgJobDev &d = T.jobs[i];
         d.n = (uint32_t)s.n;
         d.k = (uint32_t)s.k;
-        d.goff = (uint32_t)hs.size();
+        d.goff = (uint32_t)T.gsel.size();
         uint64_t key = 0;
         for (int q = 0; q < s.n; ++q) key |= (uint64_t)s.start[q] << (4 * (s.n - 1 - q));
         d.start_rank = (uint32_t)host_rank64(key, s.n);
         d.max_layers = (uint32_t)s.max_layers;
         d.pad = 0;
         d.max_frontier = s.max_frontier;
-        d.sizes_off = sizes_total;
-        sizes_total += (uint64_t)s.max_layers;
-        for (int g = 0; g < s.k; ++g) hs.push_back(make_gensel(s.n, s.gens.data() + (size_t)g * s.n));
-        if (s.n > (int)kWgLdsN) slot_words = std::max<uint64_t>(slot_words, (factorial(s.n) + 31) / 32);
+        d.sizes_off = T.sizes_total;
+        T.sizes_total += std::min<uint64_t>((uint64_t)s.max_layers, factorial(s.n));
+        for (int g = 0; g < s.k; ++g) T.gsel.push_back(make_gensel(s.n, s.gens.data() + (size_t)g * s.n));
+        if (s.n > (int)kWgLdsN) {
+            T.slot_words = std::max<uint64_t>(T.slot_words, (factorial(s.n) + 31) / 32);
+            if (slot_first) T.n_slot_jobs = i + 1;
+        }
+        T.n_max = std::max(T.n_max, s.n);
     }
-    if (hs.empty()) hs.push_back(GenSel{});
-    slot_words = (slot_words + 63) / 64 * 64;
+    if (T.gsel.empty()) T.gsel.push_back(GenSel{});
+    T.slot_words = (T.slot_words + 63) / 64 * 64;
+    return T;
+}
+
+// Copies the launch's outcomes into the callers' results.
+void wg_results(std::vector<WgItem> &items, const WgTables &T, const uint64_t *hsz, const WgOutDev *ho, double ms,
+                double t_submit, double t_admit, double t_done) {
+    for (uint32_t i = 0; i < (uint32_t)T.jobs.size(); ++i) {
+        const JobSpec &s = *items[T.order[i]].spec;
+        cg_result_t *r = items[T.order[i]].res;
+        const WgOutDev &o = ho[i];
+        std::memset(r->layer_sizes, 0, sizeof(uint64_t) * (size_t)s.max_layers);
+        const int nl = std::max(0, std::min(o.num_layers, s.max_layers));
+        std::memcpy(r->layer_sizes, hsz + T.jobs[i].sizes_off, sizeof(uint64_t) * (size_t)nl);
+        r->status = o.status;
+        r->num_layers = nl;
+        r->states_expanded = o.expanded;
+        r->candidates = o.expanded * (uint64_t)s.k;
+        r->device_ms = ms;
+        r->n_kstats = 0;
+        r->t_submit = t_submit;
+        r->t_admit = t_admit;
+        r->t_done = t_done;
+    }
+}
+
+}  // namespace
+
+double WgRunner::run(std::vector<WgItem> &items, const WgTuning &t, double t_submit) {
+    const uint32_t nj = (uint32_t)items.size();
+    if (!nj) return 0.0;
+    if (t.block < 64 || t.block > kWgMaxBlock || t.block % kWave) throw Error(CG_E_INVAL, "bad workgroup size");
+    // one queue: every workgroup owns a slot when any job needs one
+    const WgTables T = wg_tables(items, false);
+    const uint64_t sizes_total = T.sizes_total, slot_words = T.slot_words;
 
     int occ = 0;
     CG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, wg_growth_kernel, t.block, 0));
@@ -390,24 +472,25 @@ double WgRunner::run(std::vector<WgItem> &items, const WgTuning &t, double t_sub
     const uint32_t grid = (uint32_t)std::min<uint64_t>(nj, (uint64_t)device_cus() * (uint64_t)occ);
 
     jobs_.ensure(sizeof(WgJobDev) * nj, 1.25);
-    gsel_.ensure(sizeof(GenSel) * hs.size(), 1.25);
+    gsel_.ensure(sizeof(GenSel) * T.gsel.size(), 1.25);
     sizes_.ensure(sizeof(uint64_t) * sizes_total, 1.25);
     outs_.ensure(sizeof(WgOutDev) * nj, 1.25);
     ticket_.ensure(256);
     if (slot_words) ws_.ensure((size_t)grid * 3 * slot_words * sizeof(uint32_t));
-    CG_HIP(hipMemcpyAsync(jobs_.p, hj.data(), sizeof(WgJobDev) * nj, hipMemcpyHostToDevice, stream_));
-    CG_HIP(hipMemcpyAsync(gsel_.p, hs.data(), sizeof(GenSel) * hs.size(), hipMemcpyHostToDevice, stream_));
+    CG_HIP(hipMemcpyAsync(jobs_.p, T.jobs.data(), sizeof(WgJobDev) * nj, hipMemcpyHostToDevice, stream_));
+    CG_HIP(hipMemcpyAsync(gsel_.p, T.gsel.data(), sizeof(GenSel) * T.gsel.size(), hipMemcpyHostToDevice, stream_));
 
     uint32_t *gbits = slot_words ? ws_.as<uint32_t>() : nullptr;
+    const uint32_t n_slot_jobs = 0, n_slot_blocks = gbits ? grid : 0u;
     const std::vector<uint64_t> key = {(uint64_t)(uintptr_t)jobs_.p, nj, (uint64_t)(uintptr_t)gsel_.p,
                                        (uint64_t)(uintptr_t)sizes_.p, (uint64_t)(uintptr_t)outs_.p,
                                        (uint64_t)(uintptr_t)ticket_.p, (uint64_t)(uintptr_t)gbits, slot_words,
                                        grid, (uint64_t)t.block};
     auto enqueue = [&]() {
-        hipLaunchKernelGGL(clear_u32_kernel, dim3(1), dim3(64), 0, stream_, ticket_.as<uint32_t>(), 1u);
+        hipLaunchKernelGGL(clear_u32_kernel, dim3(1), dim3(64), 0, stream_, ticket_.as<uint32_t>(), 2u);
         hipLaunchKernelGGL(wg_growth_kernel, dim3(grid), dim3(t.block), 0, stream_, jobs_.as<const WgJobDev>(), nj,
-                           gsel_.as<const GenSel>(), sizes_.as<uint64_t>(), outs_.as<WgOutDev>(),
-                           ticket_.as<uint32_t>(), gbits, slot_words);
+                           n_slot_jobs, n_slot_blocks, gsel_.as<const GenSel>(), sizes_.as<uint64_t>(),
+                           outs_.as<WgOutDev>(), ticket_.as<uint32_t>(), gbits, slot_words);
     };
     if (key != graph_key_) {
         // the graph is built node by node (no stream capture): a queue
@@ -418,16 +501,17 @@ double WgRunner::run(std::vector<WgItem> &items, const WgTuning &t, double t_sub
         graph_ = nullptr;
         graph_key_.clear();
         uint32_t *tk = ticket_.as<uint32_t>();
-        uint32_t one = 1;
-        void *clear_args[] = {&tk, &one};
+        uint32_t two = 2;
+        void *clear_args[] = {&tk, &two};
         const WgJobDev *a_jobs = jobs_.as<const WgJobDev>();
-        uint32_t a_nj = nj;
+        uint32_t a_nj = nj, a_slot_jobs = n_slot_jobs, a_slot_blocks = n_slot_blocks;
         const GenSel *a_gsel = gsel_.as<const GenSel>();
         uint64_t *a_sizes = sizes_.as<uint64_t>();
         WgOutDev *a_outs = outs_.as<WgOutDev>();
         uint32_t *a_gbits = gbits;
         uint64_t a_slot = slot_words;
-        void *wg_args[] = {&a_jobs, &a_nj, &a_gsel, &a_sizes, &a_outs, &tk, &a_gbits, &a_slot};
+        void *wg_args[] = {&a_jobs, &a_nj, &a_slot_jobs, &a_slot_blocks, &a_gsel, &a_sizes, &a_outs, &tk, &a_gbits,
+                           &a_slot};
         hipKernelNodeParams p0{}, p1{};
         p0.func = reinterpret_cast<void *>(clear_u32_kernel);
         p0.gridDim = dim3(1);
@@ -480,23 +564,7 @@ double WgRunner::run(std::vector<WgItem> &items, const WgTuning &t, double t_sub
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     const double t_done = now_seconds();
-    for (uint32_t i = 0; i < nj; ++i) {
-        const JobSpec &s = *items[order[i]].spec;
-        cg_result_t *r = items[order[i]].res;
-        const WgOutDev &o = ho[i];
-        std::memset(r->layer_sizes, 0, sizeof(uint64_t) * (size_t)s.max_layers);
-        const int nl = std::min(o.num_layers, s.max_layers);
-        std::memcpy(r->layer_sizes, hsz.data() + hj[i].sizes_off, sizeof(uint64_t) * (size_t)nl);
-        r->status = o.status;
-        r->num_layers = nl;
-        r->states_expanded = o.expanded;
-        r->candidates = o.expanded * (uint64_t)s.k;
-        r->device_ms = ms;
-        r->n_kstats = 0;
-        r->t_submit = t_submit;
-        r->t_admit = t_admit;
-        r->t_done = t_done;
-    }
+    wg_results(items, T, hsz.data(), ho.data(), ms, t_submit, t_admit, t_done);
     return ms;
 }
 
@@ -528,6 +596,135 @@ WgTuning tune_wg(std::vector<WgItem> &sample, hipStream_t s) {
     std::lock_guard<std::mutex> lk(mu);
     cache[{dev, n_max}] = best;
     return best;
+}
+
+// ---------------------------------------------------------------------------
+// Small-job batches without allocation (cg_growth_batch_noalloc)
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t na_align(size_t x) { return (x + 255) & ~(size_t)255; }
+// layout of the scratch array
+constexpr size_t kNaOffTicket = 0;  // two uint32 queue tickets
+constexpr size_t kNaOffOuts = 256;
+constexpr size_t kNaOffJobs = na_align(kNaOffOuts + sizeof(WgOutDev) * kNoAllocMaxJobs);
+constexpr size_t kNaOffGsel = na_align(kNaOffJobs + sizeof(WgJobDev) * kNoAllocMaxJobs);
+constexpr size_t kNaOffSizes = na_align(kNaOffGsel + sizeof(GenSel) * kNoAllocMaxGens);
+constexpr size_t kNaOffSlots = na_align(kNaOffSizes + sizeof(uint64_t) * kNoAllocMaxSizes);
+// one n = 10 slot: three bitmaps of 10!/32 words, rounded up to 64 words
+constexpr size_t kNaSlot10 = 3 * (((factorial(10) + 31) / 32 + 63) / 64 * 64) * sizeof(uint32_t);
+static_assert(kNaOffSlots + 16 * kNaSlot10 <= kNoAllocScratchBytes, "room for at least 16 slots of n = 10");
+
+constexpr int kNaMaxDevices = 64;
+struct NaDevice {
+    std::once_flag once;
+    hipError_t err = hipSuccess;
+    void *ptr = nullptr;  // the device's address of `scratch`
+    std::mutex mu;        // one call at a time per device in this process
+};
+NaDevice g_na[kNaMaxDevices];
+
+}  // namespace
+
+void *noalloc_scratch(int dev) {
+    if (dev < 0 || dev >= kNaMaxDevices) throw Error(CG_E_DEVICE, "device index beyond the no-allocation table");
+    NaDevice &d = g_na[dev];
+    // once per device, with that device current (the caller's): each GPU
+    // holds its own copy of the array at its own address
+    std::call_once(d.once, [&] { d.err = hipGetSymbolAddress(&d.ptr, HIP_SYMBOL(scratch)); });
+    if (d.err != hipSuccess || !d.ptr)
+        throw Error(CG_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(d.err));
+    return d.ptr;
+}
+
+void run_batch_noalloc(int n_jobs, const cg_job_t *jobs, cg_result_t *results, hipStream_t stream) {
+    const double t0 = now_seconds();
+    if (n_jobs < 0 || n_jobs > (int)kNoAllocMaxJobs)
+        throw Error(CG_E_INVAL, "cg_growth_batch_noalloc takes at most 4096 jobs");
+    std::vector<JobSpec> specs;
+    specs.reserve((size_t)n_jobs);
+    std::vector<WgItem> items;
+    std::vector<int> idx;
+    for (int i = 0; i < n_jobs; ++i) {
+        cg_result_t *r = &results[i];
+        if (!r->layer_sizes) {
+            r->status = CG_E_INVAL;
+            r->num_layers = 0;
+            continue;
+        }
+        try {
+            specs.push_back(canonicalize(jobs[i], true));
+        } catch (const Error &e) {
+            r->status = e.code;
+            r->num_layers = 0;
+            continue;
+        }
+        if (!wg_eligible(specs.back())) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf,
+                          "job %d: cg_growth_batch_noalloc needs n <= 10, a permutation start and at most 128 "
+                          "generators",
+                          i);
+            throw Error(CG_E_INVAL, buf);
+        }
+        idx.push_back(i);
+    }
+    for (size_t j = 0; j < specs.size(); ++j) items.push_back({&specs[j], &results[idx[j]]});
+    if (items.empty()) return;
+    const WgTables T = wg_tables(items, true);
+    if (T.gsel.size() > kNoAllocMaxGens)
+        throw Error(CG_E_INVAL, "cg_growth_batch_noalloc takes at most 32768 distinct generators in all");
+    if (T.sizes_total > kNoAllocMaxSizes)
+        throw Error(CG_E_INVAL, "cg_growth_batch_noalloc records at most 2^21 layer sizes in all "
+                                "(sum over jobs of min(max_layers, n!))");
+    const uint32_t nj = (uint32_t)items.size();
+    int dev = 0;
+    CG_HIP(hipGetDevice(&dev));
+    unsigned char *base = static_cast<unsigned char *>(noalloc_scratch(dev));
+    std::lock_guard<std::mutex> lk(g_na[dev].mu);
+
+    uint32_t *ticket = reinterpret_cast<uint32_t *>(base + kNaOffTicket);
+    WgOutDev *outs = reinterpret_cast<WgOutDev *>(base + kNaOffOuts);
+    WgJobDev *djobs = reinterpret_cast<WgJobDev *>(base + kNaOffJobs);
+    GenSel *dgsel = reinterpret_cast<GenSel *>(base + kNaOffGsel);
+    uint64_t *dsizes = reinterpret_cast<uint64_t *>(base + kNaOffSizes);
+    uint32_t *gbits = T.slot_words ? reinterpret_cast<uint32_t *>(base + kNaOffSlots) : nullptr;
+
+    // the launch shape of cg_growth_batch for the batch's largest n
+    const int block = T.n_max >= 10 ? 1024 : (T.n_max == 9 ? 512 : 256);
+    int occ = 0;
+    CG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, wg_growth_kernel, block, 0));
+    if (occ < 1) occ = 1;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(nj, (uint64_t)device_cus() * (uint64_t)occ);
+    // workgroups that own a slot: as many as the slot area holds, at most
+    // one per job that needs one
+    uint32_t n_slot_blocks = 0;
+    if (gbits) {
+        const uint64_t slot_bytes = 3 * T.slot_words * sizeof(uint32_t);
+        const uint64_t fit = (kNoAllocScratchBytes - kNaOffSlots) / slot_bytes;
+        n_slot_blocks = (uint32_t)std::min<uint64_t>({fit, (uint64_t)grid, (uint64_t)T.n_slot_jobs});
+        if (n_slot_blocks < 1 || kNaOffSlots + (uint64_t)n_slot_blocks * slot_bytes > kNoAllocScratchBytes)
+            throw Error(CG_E_DEVICE, "no-allocation slot layout");
+    }
+    CG_HIP(hipMemcpyAsync(djobs, T.jobs.data(), sizeof(WgJobDev) * nj, hipMemcpyHostToDevice, stream));
+    CG_HIP(hipMemcpyAsync(dgsel, T.gsel.data(), sizeof(GenSel) * T.gsel.size(), hipMemcpyHostToDevice, stream));
+    // the array keeps the last call's contents: the tickets start at zero
+    hipLaunchKernelGGL(clear_u32_kernel, dim3(1), dim3(64), 0, stream, ticket, 2u);
+    CG_HIP(hipGetLastError());
+    const double t_admit = now_seconds();
+    hipLaunchKernelGGL(wg_growth_kernel, dim3(grid), dim3(block), 0, stream, (const WgJobDev *)djobs, nj,
+                       T.n_slot_jobs, n_slot_blocks, (const GenSel *)dgsel, dsizes, outs, ticket, gbits,
+                       T.slot_words);
+    CG_HIP(hipGetLastError());
+    std::vector<uint64_t> hsz(T.sizes_total);
+    std::vector<WgOutDev> ho(nj);
+    CG_HIP(hipMemcpyAsync(hsz.data(), dsizes, sizeof(uint64_t) * T.sizes_total, hipMemcpyDeviceToHost, stream));
+    CG_HIP(hipMemcpyAsync(ho.data(), outs, sizeof(WgOutDev) * nj, hipMemcpyDeviceToHost, stream));
+    CG_HIP(hipStreamSynchronize(stream));
+    const double t_done = now_seconds();
+    // no events (they would be allocated): device_ms is the host-timed span
+    // from the launch to the end of the read-back
+    wg_results(items, T, hsz.data(), ho.data(), 1e3 * (t_done - t_admit), t0, t_admit, t_done);
 }
 
 // ---------------------------------------------------------------------------

@@ -11,6 +11,7 @@
 #include "../../include/cayleygrowth.h"
 #include "../../include/cayleygrowth_testing.h"
 #include "batch.h"
+#include "bitmap.h"
 #include "engine.h"
 #include "perm_rank.h"
 
@@ -114,6 +115,15 @@ int cg_growth_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, cons
         if (n_jobs < 0 || (n_jobs > 0 && (!jobs || !results)))
             throw cg::Error(CG_E_INVAL, "bad batch arguments");
         cg::run_batch(n_jobs, jobs, results, opts);
+        return CG_OK;
+    });
+}
+
+int cg_growth_batch_noalloc(int n_jobs, const cg_job_t *jobs, cg_result_t *results, void *stream) {
+    return guarded([&]() -> int {
+        if (n_jobs < 0 || (n_jobs > 0 && (!jobs || !results)))
+            throw cg::Error(CG_E_INVAL, "bad batch arguments");
+        cg::run_batch_noalloc(n_jobs, jobs, results, (hipStream_t)stream);
         return CG_OK;
     });
 }

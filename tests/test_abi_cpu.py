@@ -85,3 +85,25 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(N, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(N.NativeLibraryMissing):
         N.lib()
+
+
+def test_noalloc_batch_rejects_sizes_beyond_its_limits():
+    """cg_growth_batch_noalloc checks its stated limits on the host, before
+    any device call."""
+    lib = N.lib()
+    with pytest.raises(api.CGError) as e:
+        api.growth_batch_noalloc([(5, I.coxeter(5))] * 4097)
+    assert e.value.code == N.CG_E_INVAL and "4096" in str(e.value)
+    with pytest.raises(api.CGError) as e:
+        api.growth_batch_noalloc([(5, I.coxeter(5)), (11, I.coxeter(11))])
+    assert e.value.code == N.CG_E_INVAL and "n <= 10" in str(e.value)
+    with pytest.raises(api.CGError) as e:
+        api.growth_batch_noalloc([(8, I.all_transpositions(8))] * 4096)  # 28 generators each
+    assert e.value.code == N.CG_E_INVAL and "32768" in str(e.value)
+    with pytest.raises(api.CGError) as e:
+        api.growth_batch_noalloc([(10, [I.transposition(10, 0, 1)])] * 4096, max_layers=1024)
+    assert e.value.code == N.CG_E_INVAL and "2^21" in str(e.value)
+    # a directed set without the flag fails its own job (nothing to launch)
+    res = api.growth_batch_noalloc([(6, I.lx(6))])
+    assert res[0].status == N.CG_E_UNSUPPORTED
+    assert lib.cg_growth_batch_noalloc(-1, None, None, None) == N.CG_E_INVAL
