@@ -185,23 +185,6 @@ def test_pancake_s12_full_run_first_layers_match_oracle(oracle_c):
         assert np.array_equal(key(got), key(exp)), d
 
 
-def test_lrx16_until_frontier_exceeds_2_31():
-    """S_16 with L, R, X: every layer up to the first one larger than 2^31.
-    The oracle's prefix (layers up to the first one above 2^26) is matched
-    exactly; beyond it the layers are checked by properties that hold at
-    any size."""
-    exp = _stored("lrx_16_prefix")["sizes"]
-    r = api.growth_ex(16, I.lrx(16), max_layers=512, max_frontier=1 << 31)
-    assert r.status == N.CG_TRUNCATED
-    assert r.sizes[: len(exp)] == exp
-    assert r.sizes[-1] > 2 ** 31 and all(x <= 2 ** 31 for x in r.sizes[:-1])
-    # closed under inverses with k = 3: every state of layer d >= 1 has a
-    # parent among its 3 neighbours, so |L_{d+1}| <= 2 |L_d|
-    for a, b in zip(r.sizes[1:], r.sizes[2:]):
-        assert b <= 2 * a
-    assert r.states_expanded == sum(r.sizes[:-1])
-
-
 @pytest.mark.parametrize("n", [2, 7, 12])
 def test_rank_on_device_matches_host(n):
     import ctypes

@@ -1,0 +1,112 @@
+"""S_16 with L, R, X: every layer up to the first one larger than 2^31, at
+full size (about 1e10 states, more than 2^32 candidates in the last
+expansions).
+
+The oracle's stored prefix pins the first layers exactly. The later layers
+rest on properties that hold at any size (paper, section "Reminder on Cayley
+graphs, diameters, growth": growth counts the vertices at each distance, so
+it is the same from every start vertex of a vertex-transitive Cayley graph,
+and it is unchanged when every generator is conjugated by one fixed h, which
+maps the graph onto an isomorphic one fixing the identity; section "Largest
+diameters found (and known) for n <= 15" relies on the same conjugation
+invariance when it searches generating sets up to conjugacy):
+  * generators conjugated by a seeded random h,
+  * a seeded random start permutation,
+  * key-range chunks forced so that the largest layers split into at least
+    four chunks (each chunk regenerates its candidates from the frontier).
+Each must give all layer sizes of the plain run. Tolerance: none.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from golden_data import GOLDEN  # noqa: E402
+from paper_2509_19162_amd import _native as N  # noqa: E402
+from paper_2509_19162_amd import api  # noqa: E402
+from paper_2509_19162_amd import inputs as I  # noqa: E402
+
+LIMIT = 1 << 31
+
+
+def _stored_prefix():
+    path = os.path.join(GOLDEN, "oracle_growth.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle fixtures not generated")
+    d = json.load(open(path))
+    if "lrx_16_prefix" not in d:
+        pytest.skip("lrx_16_prefix not in oracle fixtures")
+    return d["lrx_16_prefix"]
+
+
+def _run(gens, **kw):
+    torch.cuda.empty_cache()
+    r = api.growth_ex(16, gens, max_layers=512, max_frontier=LIMIT, **kw)
+    N.lib().cg_release_cached_memory()
+    return r
+
+
+@pytest.fixture(scope="module")
+def plain():
+    print("S_16 LRX plain run to 2^31", flush=True)
+    r = _run(I.lrx(16))
+    print("layers:", r.sizes, flush=True)
+    assert r.status == N.CG_TRUNCATED
+    return r
+
+
+def test_plain_run_matches_oracle_prefix_and_stop_rule(plain):
+    exp = _stored_prefix()
+    sizes = plain.sizes
+    # the oracle's prefix, every layer up to its first one above its limit
+    assert sizes[: len(exp["sizes"])] == exp["sizes"]
+    assert exp["sizes"][-1] > exp["max_frontier"]
+    # the stop rule: the first layer above 2^31 is recorded and not expanded
+    assert sizes[-1] > LIMIT and all(x <= LIMIT for x in sizes[:-1])
+    assert plain.states_expanded == sum(sizes[:-1])
+    assert plain.candidates == 3 * plain.states_expanded
+    # inverse-closed with k = 3: each state of layer d >= 1 has a parent
+    # among its 3 neighbours, so |L_{d+1}| <= 2 |L_d|
+    for a, b in zip(sizes[1:], sizes[2:]):
+        assert b <= 2 * a
+    # the last expansion has more than 2^32 candidates: the 64-bit offset
+    # paths of sort, dedup and compaction ran
+    assert 3 * sizes[-2] > 1 << 32
+
+
+def test_conjugated_generators_same_growth(plain):
+    rng = np.random.default_rng([I.SEED, 16, 1])
+    h = [int(x) for x in rng.permutation(16)]
+    hinv = I.inverse(h)
+    gens = [I.compose(I.compose(hinv, g), h) for g in I.lrx(16)]
+    assert gens != I.lrx(16)
+    print("S_16 LRX conjugated by", h, flush=True)
+    r = _run(gens)
+    assert r.status == N.CG_TRUNCATED
+    assert r.sizes == plain.sizes
+
+
+def test_random_start_same_growth(plain):
+    rng = np.random.default_rng([I.SEED, 16, 2])
+    start = [int(x) for x in rng.permutation(16)]
+    print("S_16 LRX from start", start, flush=True)
+    r = _run(I.lrx(16), start=start)
+    assert r.status == N.CG_TRUNCATED
+    assert r.sizes == plain.sizes
+
+
+def test_forced_chunks_same_growth(plain, monkeypatch):
+    # the largest expansion splits into at least four key-range chunks
+    c_max = 3 * max(plain.sizes[:-1])
+    cap = c_max // 5
+    monkeypatch.setenv("CG_CHUNK_CANDIDATES", str(cap))
+    print("S_16 LRX with chunks of at most", cap, "candidates", flush=True)
+    r = _run(I.lrx(16))
+    assert r.status == N.CG_TRUNCATED
+    assert r.sizes == plain.sizes
