@@ -249,6 +249,12 @@ def growth_batch_noalloc(jobs, max_layers: int = 256, stream=None,
     return out
 
 
+def release_cached_memory() -> None:
+    """Returns the library's device arena to the driver when no buffer uses
+    it (``cg_release_cached_memory``)."""
+    N.lib().cg_release_cached_memory()
+
+
 _WORKSPACE = None  # keeps the caller's tensor alive while the library uses it
 
 
