@@ -6,10 +6,12 @@ Run from the repository root: ``python tests/golden/make_oracle_fixtures.py
 
 * pancake_12:   S_12, prefix reversals (k = 11), full growth.
 * lrx_16_prefix: S_16, LRX, every layer up to and including the first one
-  larger than 2^26 (the GPU run goes on to 2^31; the oracle's hash set
-  cannot hold that many states in host memory).
+  larger than 2^28 (about 1.06e9 states; the GPU run goes on to 2^31, and
+  the oracle's hash set of about 1e10 states would not fit in host memory).
 * batch_4096:   the 4096 batched jobs (n ~ U{7..10}, 2-4 random
   permutations plus inverses), full growth each.
+* family_11:    S_11 with prefix reversals, LRX and reversals, full growth
+  each (one worker per family).
 """
 
 import json
@@ -50,6 +52,12 @@ def _batch_job(j):
 _JOBS = None
 
 
+def _family_11(fam):
+    t = time.time()
+    sizes, rc, _ = native.growth(11, I.family(fam, 11))
+    return fam, sizes, rc, round(time.time() - t, 1)
+
+
 def _init_jobs():
     global _JOBS
     _JOBS = I.batch_jobs(4096)
@@ -67,8 +75,8 @@ def main(names):
         print("pancake_12", sizes, flush=True)
     if "lrx_16_prefix" in names:
         t = time.time()
-        sizes, rc, _ = native.growth(16, I.lrx(16), max_frontier=1 << 26)
-        data["lrx_16_prefix"] = {"n": 16, "family": "lrx", "max_frontier": 1 << 26, "sizes": sizes,
+        sizes, rc, _ = native.growth(16, I.lrx(16), max_frontier=1 << 28)
+        data["lrx_16_prefix"] = {"n": 16, "family": "lrx", "max_frontier": 1 << 28, "sizes": sizes,
                                  "status": rc, "oracle_seconds": round(time.time() - t, 1)}
         _save(data)
         print("lrx_16_prefix", sizes, flush=True)
@@ -81,6 +89,15 @@ def main(names):
                               "oracle_seconds_wall": round(time.time() - t, 1)}
         _save(data)
         print("batch_4096 done", flush=True)
+
+
+    if "family_11" in names:
+        fams = ["pancake", "lrx", "reversals"]
+        with Pool(processes=len(fams)) as pool:
+            res = pool.map(_family_11, fams)
+        data["family_11"] = {f: {"sizes": sz, "status": rc, "oracle_seconds": sec} for f, sz, rc, sec in res}
+        _save(data)
+        print("family_11 done", flush=True)
 
 
 if __name__ == "__main__":
