@@ -249,20 +249,48 @@ typedef struct cg_queue cg_queue_t;
 /*
  * Jobs with n <= 13 and orbits up to 2^21 states share one group of
  * job-tagged keys (continuous batching: they join and leave at super-step
- * boundaries). Larger jobs run on separate lanes (a thread, an engine and
- * a stream each), concurrently with the group, admitted while their
- * estimated footprint fits the budget.
- *   hbm_budget_bytes  device bytes the active jobs may use together
+ * boundaries); cheap jobs (n <= 10, n! * k <= 2^22) run in a small-job
+ * lane, launch by launch. Larger jobs run on separate lanes (a thread, an
+ * engine and a stream each), concurrently with the group.
+ * Admission by device footprint: every admitted job is charged an upper
+ * bound of the device bytes it can make the queue hold, and a job is
+ * admitted only while the charges fit hbm_budget_bytes together. The one
+ * exception: a job whose bound alone exceeds the budget is admitted when no
+ * other job runs (it may then use more than the budget; its engine splits
+ * layers into key-range chunks when device memory runs short). Lanes free
+ * their device buffers when idle.
+ *   hbm_budget_bytes  device bytes the active jobs may hold together
  *                     (0 = 60% of free memory at creation)
- *   max_active        most jobs on the device at once (0 = 256)
+ *   max_active        most jobs in the shared group at once (0 = 256)
  *   max_queued        most jobs waiting (0 = 65536); beyond it CG_E_BUSY
+ *   large_lanes       lanes for large jobs (0 = 2, at most 8)
+ *   device            HIP device the queue runs on (-1 = the current one)
+ *   stream            hipStream_t the shared group runs on (NULL = a stream
+ *                     of its own); the lanes always use their own streams
  */
 typedef struct cg_queue_opts {
     uint64_t hbm_budget_bytes;
     int max_active;
     int max_queued;
-    int large_lanes;  /* lanes for large jobs (0 = 2, at most 8)            */
+    int large_lanes;
+    int device;
+    void *stream;
 } cg_queue_opts_t;
+
+/* Queue statistics (cg_queue_stats). Bytes: charged = the admitted jobs'
+   bounds; held = device bytes the queue's buffers hold, sampled after every
+   super-step and job (peaks since creation); over_bound counts jobs,
+   small-job launches and group super-steps that held more than they were
+   charged (the shared group's fixed buffers, under 16 MiB, are not
+   charged). */
+typedef struct cg_queue_stats {
+    uint64_t budget_bytes;
+    uint64_t charged_bytes, peak_charged_bytes;
+    uint64_t held_bytes, peak_held_bytes;
+    int running, queued;
+    uint64_t completed, cancelled, failed;
+    uint64_t over_bound;
+} cg_queue_stats_t;
 
 /* Creates the queue and its engine thread; NULL on failure (cg_last_error). */
 cg_queue_t *cg_queue_create(const cg_queue_opts_t *opts);
@@ -290,8 +318,13 @@ int cg_queue_wait(cg_queue_t *q, uint64_t ticket, int64_t timeout_us);
    runs to completion). Returns CG_OK or CG_E_INVAL (unknown ticket). */
 int cg_queue_cancel(cg_queue_t *q, uint64_t ticket);
 
-/* Cancels what is left, drains the engine thread, frees everything. */
+/* Cancels what is left (queued jobs retire with CG_E_CANCELLED), drains the
+   engine threads, frees everything. */
 void cg_queue_destroy(cg_queue_t *q);
+
+/* Fills *out with the queue's admission accounting and counters. Returns
+   CG_OK or CG_E_INVAL (NULL argument). */
+int cg_queue_stats(cg_queue_t *q, cg_queue_stats_t *out);
 
 /*
  * Device memory: at its first large request the library reserves one

@@ -93,6 +93,24 @@ class CgQueueOpts(ctypes.Structure):
         ("max_active", ctypes.c_int),
         ("max_queued", ctypes.c_int),
         ("large_lanes", ctypes.c_int),
+        ("device", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class CgQueueStats(ctypes.Structure):
+    _fields_ = [
+        ("budget_bytes", ctypes.c_uint64),
+        ("charged_bytes", ctypes.c_uint64),
+        ("peak_charged_bytes", ctypes.c_uint64),
+        ("held_bytes", ctypes.c_uint64),
+        ("peak_held_bytes", ctypes.c_uint64),
+        ("running", ctypes.c_int),
+        ("queued", ctypes.c_int),
+        ("completed", ctypes.c_uint64),
+        ("cancelled", ctypes.c_uint64),
+        ("failed", ctypes.c_uint64),
+        ("over_bound", ctypes.c_uint64),
     ]
 
 
@@ -136,6 +154,7 @@ SIGNATURES = [
     ("cg_queue_wait", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64]),
     ("cg_queue_cancel", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     ("cg_queue_destroy", None, [ctypes.c_void_p]),
+    ("cg_queue_stats", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CgQueueStats)]),
     ("cg_release_cached_memory", None, []),
     ("cg_set_workspace", ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t]),
     ("cg_growth_stats", ctypes.c_int, [u64p, ctypes.c_int, ctypes.POINTER(CgGrowthStats)]),

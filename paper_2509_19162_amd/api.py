@@ -306,8 +306,8 @@ class GrowthQueue:
     context manager or call ``close()``; open queues are closed at exit."""
 
     def __init__(self, budget_bytes: int = 0, max_active: int = 0, max_queued: int = 0,
-                 large_lanes: int = 0):
-        opts = N.CgQueueOpts(budget_bytes, max_active, max_queued, large_lanes)
+                 large_lanes: int = 0, device: int = -1, stream=None):
+        opts = N.CgQueueOpts(budget_bytes, max_active, max_queued, large_lanes, device, _stream_handle(stream))
         self._q = N.lib().cg_queue_create(ctypes.byref(opts))
         if not self._q:
             raise CGError(N.CG_E_DEVICE, N.lib().cg_last_error().decode())
@@ -343,6 +343,14 @@ class GrowthQueue:
 
     def cancel(self, ticket: int) -> int:
         return N.lib().cg_queue_cancel(self._q, ticket)
+
+    def stats(self) -> Dict[str, int]:
+        """Admission accounting (``cg_queue_stats``): budget, charged and
+        held device bytes with their peaks, running and queued jobs, and
+        completed / cancelled / failed counts."""
+        st = N.CgQueueStats()
+        _check(N.lib().cg_queue_stats(self._q, ctypes.byref(st)))
+        return {name: int(getattr(st, name)) for name, _ in N.CgQueueStats._fields_}
 
     def close(self):
         if self._q:

@@ -60,9 +60,30 @@ bool BatchGroup::idle() const {
 }
 
 uint64_t BatchGroup::device_bytes() const {
-    uint64_t b = cand0_.bytes + cand1_.bytes + merged_.bytes + join_.bytes + w_.status.bytes;
+    uint64_t b = cand0_.bytes + cand1_.bytes + merged_.bytes + join_.bytes + gsel_.bytes + jobs_.bytes + cnt_.bytes +
+                 pos_.bytes;
+    for (const DevBuf *x : {&w_.hist, &w_.base, &w_.small, &w_.status, &w_.bounds, &w_.tile_cnt, &w_.tile_off,
+                            &w_.kill, &w_.tcnt, &w_.toff, &w_.bsum})
+        b += x->bytes;
     for (int i = 0; i < 3; ++i) b += lay_[i].bytes;
     return b;
+}
+
+bool BatchGroup::release_idle() {
+    if (!idle()) return false;
+    CG_HIP(hipStreamSynchronize(stream_));
+    for (DevBuf *x : {&cand0_, &cand1_, &merged_, &join_, &w_.status, &w_.bounds, &w_.tile_cnt, &w_.tile_off,
+                      &w_.kill, &w_.tcnt, &w_.toff, &w_.bsum})
+        x->release();
+    w_.epoch = 0;
+    for (int i = 0; i < 3; ++i) {
+        lay_[i].release();
+        lay_[i].ensure(1024);
+    }
+    ncur_ = nprev_ = 0;
+    std::fill(quarantine_.begin(), quarantine_.end(), 0);  // no key of a finished job is left
+    for (auto &J : slot_) J.F = 0;
+    return true;
 }
 
 void BatchGroup::add(int slot, const JobSpec &spec, cg_result_t *res, double t_submit, double t_admit) {
@@ -132,10 +153,10 @@ void BatchGroup::step(std::vector<int> &finished) {
     if (!pending_keys_.empty()) {
         std::sort(pending_keys_.begin(), pending_keys_.end());
         const uint64_t np = pending_keys_.size();
-        join_.ensure(np * sizeof(uint64_t), 1.5);
+        join_.fit(np * sizeof(uint64_t), 1.5);
         CG_HIP(hipMemcpyAsync(join_.p, pending_keys_.data(), np * sizeof(uint64_t), hipMemcpyHostToDevice,
                               stream_));
-        merged_.ensure((ncur_ + np) * sizeof(uint64_t), 1.5);
+        merged_.fit((ncur_ + np) * sizeof(uint64_t), 1.5);
         launch_merge(lay_[ic_].as<uint64_t>(), ncur_, join_.as<uint64_t>(), np, merged_.as<uint64_t>(), stream_);
         lay_[ic_].swap(merged_);
         ncur_ += np;
@@ -187,8 +208,8 @@ void BatchGroup::step(std::vector<int> &finished) {
     CG_HIP(hipMemcpyAsync(jobs_.p, tab.data(), sizeof(BatchJobDev) * S, hipMemcpyHostToDevice, stream_));
 
     // 3. expand, sort, unique + set difference, compaction, per-job counts
-    cand0_.ensure(C * sizeof(uint64_t) + 64, 1.25);
-    cand1_.ensure(C * sizeof(uint64_t) + 64, 1.25);
+    cand0_.fit(C * sizeof(uint64_t) + 64, 1.25);
+    cand1_.fit(C * sizeof(uint64_t) + 64, 1.25);
     launch_batch_expand(lay_[ic_].as<uint64_t>(), ncur_, jobs_.as<BatchJobDev>(), gsel_.as<GenSel>(),
                         cand0_.as<uint64_t>(), shift_, C, (uint32_t)S, w_);
     const int hi = std::min(64, shift_ + tag_bits_);
@@ -203,7 +224,7 @@ void BatchGroup::step(std::vector<int> &finished) {
     const uint64_t N = host_[0];
     if (((uint32_t *)(host_ + 1))[0] != 0) throw Error(CG_E_DEVICE, "kernel error flag set in a batch step");
     if (N > C) throw Error(CG_E_DEVICE, "batch layer size out of range");
-    lay_[in_].ensure(std::max<uint64_t>(N, 1) * sizeof(uint64_t) + 64, 1.25);
+    lay_[in_].fit(std::max<uint64_t>(N, 1) * sizeof(uint64_t) + 64, 1.25);
     launch_dedup_gather(scratch, lay_[in_].as<uint64_t>(), N, w_);
     launch_tag_count(lay_[in_].as<uint64_t>(), N, shift_, cnt_.as<unsigned long long>(),
                      pos_.as<unsigned long long>(), (uint32_t)S, w_);

@@ -62,6 +62,10 @@ public:
     void cancel(int slot);
     bool occupied(int slot) const { return slot >= 0 && slot < (int)slot_.size() && slot_[slot].res; }
     uint64_t device_bytes() const;
+    // With no job running: drops the keys finished jobs left in the layer
+    // windows (their slots become free at once) and frees the large
+    // buffers. Returns false (and does nothing) while a job runs.
+    bool release_idle();
 
 private:
     void finish(int slot, int status);

@@ -55,6 +55,11 @@ public:
     // Runs every item to completion and fills its result. Returns the
     // device time of the launch in ms.
     double run(std::vector<WgItem> &items, const WgTuning &t, double t_submit);
+    // An upper bound of the device bytes one launch of `items` holds.
+    static uint64_t launch_bytes(const std::vector<WgItem> &items, const WgTuning &t);
+    // Device bytes the runner holds now; release() frees them.
+    uint64_t device_bytes() const;
+    void release();
     int graph_launches() const { return graph_launches_; }
     int graph_captures() const { return graph_captures_; }
 

@@ -458,30 +458,61 @@ void wg_results(std::vector<WgItem> &items, const WgTables &T, const uint64_t *h
 
 }  // namespace
 
+// Workgroups of a launch: every job its own, at most as many as are
+// resident at once.
+static uint32_t wg_grid(uint32_t n_jobs, int block) {
+    int occ = 0;
+    CG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, wg_growth_kernel, block, 0));
+    if (occ < 1) occ = 1;
+    return (uint32_t)std::min<uint64_t>(n_jobs, (uint64_t)device_cus() * (uint64_t)occ);
+}
+
+uint64_t WgRunner::launch_bytes(const std::vector<WgItem> &items, const WgTuning &t) {
+    if (items.empty()) return 0;
+    const WgTables T = wg_tables(items, true);
+    const uint32_t nj = (uint32_t)items.size();
+    const uint64_t slots = T.slot_words ? std::min<uint64_t>(wg_grid(nj, t.block), T.n_slot_jobs) : 0;
+    // every buffer as DevBuf rounds it (64 KiB) with its growth slack
+    auto r = [](uint64_t b) { return ((uint64_t)(1.5 * (double)b) + (64u << 10) - 1) / (64u << 10) * (64u << 10); };
+    return r(sizeof(WgJobDev) * nj) + r(sizeof(GenSel) * T.gsel.size()) + r(sizeof(uint64_t) * T.sizes_total) +
+           r(sizeof(WgOutDev) * nj) + r(256) + r(slots * 3 * T.slot_words * sizeof(uint32_t));
+}
+
+uint64_t WgRunner::device_bytes() const {
+    return jobs_.bytes + gsel_.bytes + sizes_.bytes + outs_.bytes + ws_.bytes + ticket_.bytes;
+}
+
+void WgRunner::release() {
+    if (exec_) (void)hipGraphExecDestroy(exec_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+    exec_ = nullptr;
+    graph_ = nullptr;
+    graph_key_.clear();
+    for (DevBuf *b : {&jobs_, &gsel_, &sizes_, &outs_, &ws_, &ticket_}) b->release();
+}
+
 double WgRunner::run(std::vector<WgItem> &items, const WgTuning &t, double t_submit) {
     const uint32_t nj = (uint32_t)items.size();
     if (!nj) return 0.0;
     if (t.block < 64 || t.block > kWgMaxBlock || t.block % kWave) throw Error(CG_E_INVAL, "bad workgroup size");
-    // one queue: every workgroup owns a slot when any job needs one
-    const WgTables T = wg_tables(items, false);
+    // jobs that need a device slot first: only as many workgroups as there
+    // are such jobs own one
+    const WgTables T = wg_tables(items, true);
     const uint64_t sizes_total = T.sizes_total, slot_words = T.slot_words;
-
-    int occ = 0;
-    CG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, wg_growth_kernel, t.block, 0));
-    if (occ < 1) occ = 1;
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(nj, (uint64_t)device_cus() * (uint64_t)occ);
+    const uint32_t grid = wg_grid(nj, t.block);
+    const uint32_t n_slot_jobs = T.n_slot_jobs;
+    const uint32_t n_slot_blocks = slot_words ? std::min(grid, n_slot_jobs) : 0u;
 
     jobs_.ensure(sizeof(WgJobDev) * nj, 1.25);
     gsel_.ensure(sizeof(GenSel) * T.gsel.size(), 1.25);
     sizes_.ensure(sizeof(uint64_t) * sizes_total, 1.25);
     outs_.ensure(sizeof(WgOutDev) * nj, 1.25);
     ticket_.ensure(256);
-    if (slot_words) ws_.ensure((size_t)grid * 3 * slot_words * sizeof(uint32_t));
+    if (slot_words) ws_.ensure((size_t)n_slot_blocks * 3 * slot_words * sizeof(uint32_t));
     CG_HIP(hipMemcpyAsync(jobs_.p, T.jobs.data(), sizeof(WgJobDev) * nj, hipMemcpyHostToDevice, stream_));
     CG_HIP(hipMemcpyAsync(gsel_.p, T.gsel.data(), sizeof(GenSel) * T.gsel.size(), hipMemcpyHostToDevice, stream_));
 
     uint32_t *gbits = slot_words ? ws_.as<uint32_t>() : nullptr;
-    const uint32_t n_slot_jobs = 0, n_slot_blocks = gbits ? grid : 0u;
     const std::vector<uint64_t> key = {(uint64_t)(uintptr_t)jobs_.p, nj, (uint64_t)(uintptr_t)gsel_.p,
                                        (uint64_t)(uintptr_t)sizes_.p, (uint64_t)(uintptr_t)outs_.p,
                                        (uint64_t)(uintptr_t)ticket_.p, (uint64_t)(uintptr_t)gbits, slot_words,
@@ -692,10 +723,7 @@ void run_batch_noalloc(int n_jobs, const cg_job_t *jobs, cg_result_t *results, h
 
     // the launch shape of cg_growth_batch for the batch's largest n
     const int block = T.n_max >= 10 ? 1024 : (T.n_max == 9 ? 512 : 256);
-    int occ = 0;
-    CG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, wg_growth_kernel, block, 0));
-    if (occ < 1) occ = 1;
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(nj, (uint64_t)device_cus() * (uint64_t)occ);
+    const uint32_t grid = wg_grid(nj, block);
     // workgroups that own a slot: as many as the slot area holds, at most
     // one per job that needs one
     uint32_t n_slot_blocks = 0;

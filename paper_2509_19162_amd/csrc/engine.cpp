@@ -136,6 +136,29 @@ Engine::~Engine() {
     }
 }
 
+uint64_t Engine::device_bytes() const {
+    uint64_t b = 0;
+    for (const DevBuf *x : {&gsel_, &cand0_, &cand1_, &lay_[0], &lay_[1], &lay_[2], &arena_, &stage_, &chunk_hist_,
+                            &vis_[0], &vis_[1], &rk_[0], &rk_[1], &rk_[2]})
+        b += x->bytes;
+    for (const DevBuf *x : {&w_.hist, &w_.base, &w_.small, &w_.status, &w_.bounds, &w_.tile_cnt, &w_.tile_off,
+                            &w_.kill, &w_.tcnt, &w_.toff, &w_.bsum})
+        b += x->bytes;
+    if (wg_) b += wg_->device_bytes();
+    return b;
+}
+
+void Engine::release_buffers() {
+    if (wg_) wg_->release();
+    for (DevBuf *x : {&gsel_, &cand0_, &cand1_, &lay_[0], &lay_[1], &lay_[2], &arena_, &stage_, &chunk_hist_,
+                      &vis_[0], &vis_[1], &rk_[0], &rk_[1], &rk_[2]})
+        x->release();
+    // the pipeline's small buffers stay (init sized them); the large ones go
+    for (DevBuf *x : {&w_.status, &w_.bounds, &w_.tile_cnt, &w_.tile_off, &w_.kill, &w_.tcnt, &w_.toff, &w_.bsum})
+        x->release();
+    w_.epoch = 0;
+}
+
 uint64_t Engine::read_counter() {
     // the error flag and the counter lie in one small device buffer: one
     // copy brings both

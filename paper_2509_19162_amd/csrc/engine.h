@@ -46,6 +46,10 @@ public:
     hipStream_t stream() const { return stream_; }
     // Reads back one u64 counter and the kernel error flag (synchronises).
     uint64_t read_counter();
+    // Device bytes the engine's buffers hold now (they are kept between
+    // runs); release_buffers() frees them.
+    uint64_t device_bytes() const;
+    void release_buffers();
 
 private:
     void export_layer(const JobSpec &spec, const uint64_t *d_keys, uint64_t count,

@@ -97,6 +97,12 @@ struct DevBuf {
     // Grow to at least `need` bytes (contents are not kept). Returns true if
     // the buffer was reallocated. Memory comes from the device arena.
     bool ensure(size_t need, double slack = 1.0);
+    // ensure(), after freeing a buffer more than 1.25 x need + 64 MiB large
+    // (a shared buffer shrinks when the jobs that grew it have left)
+    bool fit(size_t need, double slack = 1.0) {
+        if (p && bytes > need + need / 4 + (64u << 20)) release();
+        return ensure(need, slack);
+    }
     void release();
     // Exchanges the memory of two buffers (with where it came from; the
     // streams stay with their owners).

@@ -3,6 +3,14 @@ import sys
 
 import pytest
 
+# torch first: its HIP runtime must be the one in the process before the
+# library (which links the system HIP runtime) is loaded, or torch's own
+# device initialisation can fail later in the same process
+try:
+    import torch  # noqa: F401
+except ImportError:  # the CPU suite runs without it
+    torch = None
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

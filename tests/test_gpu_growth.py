@@ -212,9 +212,43 @@ def test_ranked_and_packed_sorts_agree(fam, n, oracle_c):
     assert a.sizes == b.sizes
     if n <= 9:
         assert a.sizes == oracle_c.growth(n, gens)[0]
+    elif fam == "all_transpositions":
+        assert a.sizes == transposition_growth(n)  # Stirling numbers of the first kind
+    else:
+        assert a.sizes == _stored(f"family_{n}")[fam]["sizes"]
     # same layer contents on a small case
     if n == 5:
         ea = api.growth_ex(n, gens, export_layers=120)
         eb = api.growth_ex(n, gens, export_layers=120, packed_sort=True)
         for x, y in zip(ea.layers, eb.layers):
             assert np.array_equal(x, y)
+
+
+def test_growth_from_several_host_threads(oracle_c):
+    """cg_growth from eight host threads at once (each call runs on a stream
+    of its own), three calls each, every result checked against the
+    oracle."""
+    import threading
+
+    jobs = [(n, I.family(fam, n)) for n, fam in
+            [(8, "coxeter"), (9, "pancake"), (7, "all_transpositions"), (9, "lrx"), (8, "star"),
+             (9, "reversals"), (6, "coxeter"), (9, "star")]]
+    got = [[] for _ in jobs]
+    errors = []
+
+    def work(i):
+        try:
+            for _ in range(3):
+                got[i].append(api.growth(*jobs[i], max_layers=256))
+        except Exception as e:  # surfaced below
+            errors.append(e)
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(len(jobs))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    for (n, g), runs in zip(jobs, got):
+        exp = oracle_c.growth(n, g)[0]
+        assert runs == [exp] * 3, n
