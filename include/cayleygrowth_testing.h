@@ -95,6 +95,17 @@ int cg_test_unrank(int n, const uint32_t *h_ranks, uint64_t count, uint64_t *h_k
                    int on_device, void *stream);
 
 /*
+ * The same with 64-bit ranks, for n = 13..16 (16! < 2^45): the rank and
+ * unrank that the growth kernels use when candidates of such permutations
+ * are sorted and compared as lexicographic ranks. CG_E_INVAL for n outside
+ * 13..16 or (unrank) a rank >= n!.
+ */
+int cg_test_rank64(int n, const uint64_t *h_keys, uint64_t count, uint64_t *h_ranks,
+                   int on_device, void *stream);
+int cg_test_unrank64(int n, const uint64_t *h_ranks, uint64_t count, uint64_t *h_keys,
+                     int on_device, void *stream);
+
+/*
  * Plain device-to-device copy of `bytes` bytes (a multiple of 16, both
  * pointers 16-byte aligned), run `repeats` times. Not part of the method:
  * the known byte count calibrates hardware traffic counters against the

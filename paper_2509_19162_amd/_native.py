@@ -175,6 +175,10 @@ SIGNATURES = [
      [ctypes.c_int, u64p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int, ctypes.c_void_p]),
     ("cg_test_unrank", ctypes.c_int,
      [ctypes.c_int, ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint64, u64p, ctypes.c_int, ctypes.c_void_p]),
+    ("cg_test_rank64", ctypes.c_int,
+     [ctypes.c_int, u64p, ctypes.c_uint64, u64p, ctypes.c_int, ctypes.c_void_p]),
+    ("cg_test_unrank64", ctypes.c_int,
+     [ctypes.c_int, u64p, ctypes.c_uint64, u64p, ctypes.c_int, ctypes.c_void_p]),
     ("cg_test_host_expand", ctypes.c_int, [ctypes.c_int, u8p, ctypes.c_int, u64p, ctypes.c_uint64, u64p]),
     ("cg_test_copy", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]),

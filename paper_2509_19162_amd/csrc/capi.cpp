@@ -349,6 +349,18 @@ __global__ void unrank_kernel(const uint32_t *r, uint64_t count, uint64_t *k) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) k[i] = cg::perm_unrank_t<N>(r[i]);
 }
+
+template <int N>
+__global__ void rank64_kernel(const uint64_t *k, uint64_t count, uint64_t *r) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) r[i] = cg::perm_rank_t<N, uint64_t>(k[i]);
+}
+
+template <int N>
+__global__ void unrank64_kernel(const uint64_t *r, uint64_t count, uint64_t *k) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) k[i] = cg::perm_unrank_t<N, uint64_t>(r[i]);
+}
 }
 
 // v_perm_b32: byte j of the result selects from the 8-byte {s0:s1} (s1 the
@@ -432,6 +444,59 @@ int cg_test_unrank(int n, const uint32_t *h_ranks, uint64_t count, uint64_t *h_k
         CG_HIP(hipStreamSynchronize(s));
         return CG_OK;
     });
+}
+
+// 64-bit ranks (n = 13..16): the code of the growth kernels, on the host
+// or on the device. kind 0 = rank (in: packed keys), 1 = unrank (in: ranks).
+static int rank64_impl(int kind, int n, const uint64_t *h_in, uint64_t count, uint64_t *h_out, int on_device,
+                       void *stream) {
+    return guarded([&]() -> int {
+        if (n < cg::kRankMaxN + 1 || n > cg::kRank64MaxN || (count && (!h_in || !h_out)))
+            throw cg::Error(CG_E_INVAL, "bad 64-bit rank arguments (n must be 13..16)");
+        if (kind == 1) {
+            uint64_t fact = 1;
+            for (int i = 2; i <= n; ++i) fact *= (uint64_t)i;
+            for (uint64_t i = 0; i < count; ++i)
+                if (h_in[i] >= fact) throw cg::Error(CG_E_INVAL, "rank out of range");
+        }
+        if (!on_device) {
+            cg::with_rank64_n(n, [&](auto NN) {
+                constexpr int N = decltype(NN)::value;
+                for (uint64_t i = 0; i < count; ++i)
+                    h_out[i] = kind == 0 ? cg::perm_rank_t<N, uint64_t>(h_in[i]) : cg::perm_unrank_t<N, uint64_t>(h_in[i]);
+            });
+            return CG_OK;
+        }
+        if (!count) return CG_OK;
+        hipStream_t s = (hipStream_t)stream;
+        cg::DevBuf a, b;
+        a.stream = b.stream = s;
+        a.ensure(count * 8);
+        b.ensure(count * 8);
+        CG_HIP(hipMemcpyAsync(a.p, h_in, count * 8, hipMemcpyHostToDevice, s));
+        const dim3 grid((uint32_t)((count + 255) / 256));
+        cg::with_rank64_n(n, [&](auto NN) {
+            constexpr int N = decltype(NN)::value;
+            if (kind == 0)
+                hipLaunchKernelGGL(rank64_kernel<N>, grid, dim3(256), 0, s, a.as<uint64_t>(), count, b.as<uint64_t>());
+            else
+                hipLaunchKernelGGL(unrank64_kernel<N>, grid, dim3(256), 0, s, a.as<uint64_t>(), count,
+                                   b.as<uint64_t>());
+        });
+        CG_HIP(hipGetLastError());
+        CG_HIP(hipMemcpyAsync(h_out, b.p, count * 8, hipMemcpyDeviceToHost, s));
+        CG_HIP(hipStreamSynchronize(s));
+        return CG_OK;
+    });
+}
+
+int cg_test_rank64(int n, const uint64_t *h_keys, uint64_t count, uint64_t *h_ranks, int on_device, void *stream) {
+    return rank64_impl(0, n, h_keys, count, h_ranks, on_device, stream);
+}
+
+int cg_test_unrank64(int n, const uint64_t *h_ranks, uint64_t count, uint64_t *h_keys, int on_device,
+                     void *stream) {
+    return rank64_impl(1, n, h_ranks, count, h_keys, on_device, stream);
 }
 
 int cg_test_copy(const void *d_src, void *d_dst, uint64_t bytes, int repeats, void *stream) {

@@ -61,6 +61,7 @@ __device__ __forceinline__ uint32_t pad(uint32_t i) { return i + (i >> 4); }
 struct PackedKeys {
     using K = uint64_t;
     using Ref = uint64_t;  // reference layers as stored
+    static constexpr bool kConvert = false;  // survivors are moved as they are
     int n;
     __device__ __forceinline__ K from_layer(uint64_t x) const { return x; }
     __device__ __forceinline__ uint64_t to_layer(K x) const { return x; }
@@ -69,6 +70,7 @@ template <int N>
 struct RankedKeys {
     using K = uint32_t;
     using Ref = uint64_t;
+    static constexpr bool kConvert = true;
     int n;
     __device__ __forceinline__ K from_layer(uint64_t x) const { return perm_rank_t<N>(x); }
     __device__ __forceinline__ uint64_t to_layer(K x) const { return perm_unrank_t<N>(x); }
@@ -79,9 +81,20 @@ template <int N>
 struct RankedRefs {
     using K = uint32_t;
     using Ref = uint32_t;
+    static constexpr bool kConvert = true;
     int n;
     __device__ __forceinline__ K from_layer(uint32_t x) const { return x; }
     __device__ __forceinline__ uint64_t to_layer(K x) const { return perm_unrank_t<N>(x); }
+};
+// Candidates as 64-bit ranks (n = 13..16); reference layers packed.
+template <int N>
+struct Ranked64Keys {
+    using K = uint64_t;
+    using Ref = uint64_t;
+    static constexpr bool kConvert = true;
+    int n;
+    __device__ __forceinline__ K from_layer(uint64_t x) const { return perm_rank_t<N, uint64_t>(x); }
+    __device__ __forceinline__ uint64_t to_layer(K x) const { return perm_unrank_t<N, uint64_t>(x); }
 };
 
 // bounds[4t + 0/1]: lower bound of tile t's first key / upper bound of its
@@ -341,7 +354,7 @@ __global__ __launch_bounds__(kScanBlock) void count_scan_kernel(
 // there one tile per block measured faster.
 template <class P>
 constexpr int gather_tiles() {
-    return sizeof(typename P::K) == 4 ? kGatherTiles : 1;
+    return P::kConvert ? kGatherTiles : 1;
 }
 
 template <class P>
@@ -493,6 +506,19 @@ void launch_dedup_count_ranked_refs(int n, const uint32_t *sorted, uint64_t C, c
                                     PipeWork &w) {
     with_rank_n(n, [&](auto NN) {
         dedup_count_impl(RankedRefs<decltype(NN)::value>{n}, sorted, C, a, na, b, nb, tmp, d_count, w);
+    });
+}
+
+void launch_dedup_count_ranked64(int n, const uint64_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,
+                                 const uint64_t *b, uint64_t nb, uint64_t *tmp, uint64_t *d_count, PipeWork &w) {
+    with_rank64_n(n, [&](auto NN) {
+        dedup_count_impl(Ranked64Keys<decltype(NN)::value>{n}, sorted, C, a, na, b, nb, tmp, d_count, w);
+    });
+}
+
+void launch_dedup_gather_ranked64(int n, const uint64_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w) {
+    with_rank64_n(n, [&](auto NN) {
+        dedup_gather_impl(Ranked64Keys<decltype(NN)::value>{n}, tmp, out, out_cap, w);
     });
 }
 

@@ -439,6 +439,18 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
         }
     }
     const bool ranked = perm_start && !(spec.flags & CG_PACKED_SORT);
+    // n = 13..16 with a permutation start: candidates sort as 64-bit ranks
+    // (45 bits at n = 16: 6 passes of 8 bits instead of 8 over the 60 bits
+    // of a packed key); reference layers are ranked as the dedup reads them
+    bool perm_any = n > kRankMaxN;
+    {
+        bool seen[16] = {false};
+        for (int i = 0; i < n && perm_any; ++i) {
+            if (spec.start[i] >= n || seen[spec.start[i]]) perm_any = false;
+            else seen[spec.start[i]] = true;
+        }
+    }
+    const bool ranked64 = perm_any && !(spec.flags & CG_PACKED_SORT);
     // Ranked runs keep the 32-bit ranks of layers d-1 and d beside the packed
     // layers (written by the gather), so the set difference does not rank its
     // reference keys again. A layer from the chunked path has none; the next
@@ -452,7 +464,7 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
         rk_cur = rk_prev = true;  // layer -1 is empty
     }
     int rank_bits = 0;
-    while (rank_bits < 32 && (1ull << rank_bits) < spec.orbit_bound) ++rank_bits;
+    while (rank_bits < 63 && (1ull << rank_bits) < spec.orbit_bound) ++rank_bits;
     int layers = 1;
     int status = CG_OK;
     for (;;) {
@@ -552,6 +564,18 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             }
             launch_dedup_gather_ranked(n, scratch, out, keep_all ? out_cap : N, w_, rank_out);
             rk_next = rank_out != nullptr;
+        } else if (ranked64) {
+            uint64_t *c0 = cand0_.as<uint64_t>(), *c1 = cand1_.as<uint64_t>();
+            const uint64_t *sorted = expand_rank_sort64(n, Ld, F, gsel_.as<GenSel>(), k, c0, c1, rank_bits, w_);
+            uint64_t *scratch = sorted == c0 ? c1 : c0;
+            launch_dedup_count_ranked64(n, sorted, C, Ra, na, Rb, nb, scratch, w_.counter(), w_);
+            N = read_counter();
+            if (N > C || N > room) throw Error(CG_E_DEVICE, "layer size out of range (device error)");
+            if (!keep_all) {
+                lay_[in].ensure(std::max<uint64_t>(N, 1) * sizeof(uint64_t), 1.25);
+                out = lay_[in].as<uint64_t>();
+            }
+            launch_dedup_gather_ranked64(n, scratch, out, keep_all ? out_cap : N, w_);
         } else {
             const uint64_t *sorted = expand_sort(Ld, F, gsel_.as<GenSel>(), k, cand0_.as<uint64_t>(),
                                                  cand1_.as<uint64_t>(), bit_lo, bit_hi, w_);

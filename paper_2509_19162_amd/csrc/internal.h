@@ -187,6 +187,10 @@ uint64_t *radix_sort(uint64_t *keys, uint64_t *tmp, uint64_t count, int bit_lo,
 // boundary by k*n uint32 source shifts 4(n-1-g[i]).
 uint32_t *expand_rank_sort(int n, const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, const uint8_t *d_gfix,
                            int k, uint32_t *buf0, uint32_t *buf1, int rank_bits, PipeWork &w);
+// The same for n = 13..16 with 64-bit ranks (full ranks, no incremental
+// digits): sorts on bits [0, rank_bits), rank_bits = ceil(log2 n!).
+uint64_t *expand_rank_sort64(int n, const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,
+                             uint64_t *buf0, uint64_t *buf1, int rank_bits, PipeWork &w);
 // The same for 32-bit keys (candidates under their lexicographic rank).
 uint32_t *radix_sort32(uint32_t *keys, uint32_t *tmp, uint64_t count, int bit_lo,
                        int bit_hi, PipeWork &w);
@@ -227,6 +231,12 @@ void launch_dedup_gather_ranked(int n, const uint32_t *tmp, uint64_t *out, uint6
 void launch_dedup_count_ranked_refs(int n, const uint32_t *sorted, uint64_t C, const uint32_t *a, uint64_t na,
                                     const uint32_t *b, uint64_t nb, uint32_t *tmp, uint64_t *d_count,
                                     PipeWork &w);
+// Dedup with candidates as 64-bit lexicographic ranks (n = 13..16): the
+// reference layers (packed keys) are ranked as they are read; survivors are
+// written back as packed keys.
+void launch_dedup_count_ranked64(int n, const uint64_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,
+                                 const uint64_t *b, uint64_t nb, uint64_t *tmp, uint64_t *d_count, PipeWork &w);
+void launch_dedup_gather_ranked64(int n, const uint64_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w);
 // Permute-expand into 32-bit ranks: out[g*F + f] = rank(key(s_f . g)).
 void launch_expand_ranked(int n, const uint64_t *frontier, uint64_t F, const GenSel *d_gsel,
                           int k, uint32_t *out, PipeWork &w);

@@ -14,7 +14,8 @@
 
 namespace cg {
 
-constexpr int kRankMaxN = 12;
+constexpr int kRankMaxN = 12;    // 32-bit ranks
+constexpr int kRank64MaxN = 16;  // 64-bit ranks (16! < 2^45)
 
 __host__ __device__ __forceinline__ uint32_t perm_rank(uint64_t key, int n) {
     uint32_t rank = 0, used = 0;
@@ -68,6 +69,16 @@ constexpr int rank_split() {
     return i;
 }
 
+// Radix of the low part of the split Horner sum: the product of the radices
+// N-i of positions kHi+1 .. N-2, i.e. (N-1-kHi)!. It stays below 2^24 for
+// every N <= 16 (16: 10! = 3628800), so the low part is 24-bit work too.
+template <int N>
+constexpr uint32_t rank_lo_radix() {
+    uint32_t r = 1;
+    for (int i = rank_split<N>() + 1; i < N - 1; ++i) r *= (uint32_t)(N - i);
+    return r;
+}
+
 // The same with n fixed at compile time: the loops unroll, shifts become
 // constants and the divisions of the unrank become multiplications. R is
 // the rank type: uint32_t up to n = 12, uint64_t beyond (16! < 2^45).
@@ -78,31 +89,37 @@ __host__ __device__ __forceinline__ R perm_rank_t(uint64_t key) {
     // position has c_0 = s[0]; the last always has c = 0.
     //
     // The Horner sum is split in two: positions 0..kHi accumulate in `hi`,
-    // whose bound N (N-1) ... (N-kHi) stays below 2^24, the rest in `lo`;
-    // rank = hi * (product of the later radices) + lo. Every step is then a
-    // 24-bit multiply-add (full rate) instead of a 32-bit multiply.
+    // whose bound N (N-1) ... (N-kHi) stays below 2^24, the rest in `lo`
+    // (below rank_lo_radix<N>() < 2^24); rank = hi * lo_radix + lo. Every
+    // step is then a 24-bit multiply-add (full rate) instead of a 32- or
+    // 64-bit multiply; a 64-bit rank takes one 64-bit multiply-add at the
+    // end.
     if constexpr (N <= 1) {
         return 0;
     } else {
         constexpr int kHi = rank_split<N>();
+        constexpr uint32_t kLoRadix = rank_lo_radix<N>();
+        static_assert(kLoRadix < (1u << 24), "low part of the rank in 24 bits");
+        static_assert(sizeof(R) == 8 || N <= 12, "32-bit ranks up to n = 12");
         uint32_t unused = (1u << N) - 1u;
         const uint32_t v0 = (uint32_t)(key >> (4 * (N - 1))) & 15u;
-        R hi = (R)v0, lo = 0;
-        R lo_radix = 1;
+        uint32_t hi = v0, lo = 0;
         unused ^= 1u << v0;
 #pragma unroll
         for (int i = 1; i < N - 1; ++i) {
             const uint32_t v = (uint32_t)(key >> (4 * (N - 1 - i))) & 15u;
             const uint32_t c = (uint32_t)__builtin_popcount(low_bits(unused, v));
-            if (i <= kHi) {
-                hi = mad24<R>(hi, (R)(N - i), (R)c);
-            } else {
-                lo = mad24<R>(lo, (R)(N - i), (R)c);
-                lo_radix *= (R)(N - i);
-            }
+            if (i <= kHi)
+                hi = mad24<uint32_t>(hi, (uint32_t)(N - i), c);
+            else
+                lo = mad24<uint32_t>(lo, (uint32_t)(N - i), c);
             unused ^= 1u << v;
         }
-        return mad24<R>(hi, lo_radix, lo);  // the last position's digit is 0 (radix 1)
+        // the last position's digit is 0 (radix 1)
+        if constexpr (sizeof(R) == 4)
+            return mad24<uint32_t>(hi, kLoRadix, lo);
+        else
+            return (uint64_t)hi * (uint64_t)kLoRadix + (uint64_t)lo;
     }
 }
 
@@ -111,14 +128,33 @@ __host__ __device__ __forceinline__ R perm_rank_t(uint64_t key) {
 // entries 0-7, hi: entries 8-15), so every step is 32-bit work: read entry
 // c, then move the entries after it down one nibble, from hi into lo where
 // the list still reaches into hi (decided at compile time per position).
+// A 64-bit rank is split once, by one division by rank_lo_radix<N>(), into
+// two parts below 2^24 whose digits come from 32-bit divisions.
 template <int N, class R = uint32_t>
 __host__ __device__ __forceinline__ uint64_t perm_unrank_t(R rank) {
     static_assert(N <= 16, "16 nibbles at most");
     uint32_t c[N > 0 ? N : 1];
+    if constexpr (sizeof(R) == 8 && N > 1) {
+        constexpr int kHi = rank_split<N>();
+        constexpr uint64_t kLoRadix = rank_lo_radix<N>();
+        const uint64_t q = rank / kLoRadix;
+        uint32_t lo = (uint32_t)(rank - q * kLoRadix), hi = (uint32_t)q;
 #pragma unroll
-    for (int i = N - 1; i >= 0; --i) {
-        c[i] = (uint32_t)(rank % (R)(N - i));
-        rank /= (R)(N - i);
+        for (int i = N - 1; i > kHi; --i) {
+            c[i] = lo % (uint32_t)(N - i);
+            lo /= (uint32_t)(N - i);
+        }
+#pragma unroll
+        for (int i = kHi; i >= 0; --i) {
+            c[i] = hi % (uint32_t)(N - i);
+            hi /= (uint32_t)(N - i);
+        }
+    } else {
+#pragma unroll
+        for (int i = N - 1; i >= 0; --i) {
+            c[i] = (uint32_t)(rank % (R)(N - i));
+            rank /= (R)(N - i);
+        }
     }
     uint32_t lo = 0, hi = 0;
 #pragma unroll
@@ -156,6 +192,18 @@ __host__ __device__ __forceinline__ uint64_t perm_unrank_t(R rank) {
             klo |= v << pos;
     }
     return ((uint64_t)khi << 32) | klo;
+}
+
+// Calls f(std::integral_constant<int, N>{}) for the runtime n in 13..16:
+// the groups whose ranks need 64 bits (13! > 2^32).
+template <class F>
+void with_rank64_n(int n, F &&f) {
+    switch (n) {
+        case 13: f(std::integral_constant<int, 13>{}); break;
+        case 14: f(std::integral_constant<int, 14>{}); break;
+        case 15: f(std::integral_constant<int, 15>{}); break;
+        default: f(std::integral_constant<int, 16>{}); break;
+    }
 }
 
 // Calls f(std::integral_constant<int, N>{}) for the runtime n in 1..12.

@@ -61,17 +61,30 @@ constexpr int kWaves = kBlock / kWave;
 #ifndef CG_SORT_SPLIT64
 #define CG_SORT_SPLIT64 2
 #endif
+// 64-bit keys: 768 threads x 16 keys (12288-key tiles). A pass writes each
+// digit's run of a tile contiguously; uniformly spread digits (64-bit
+// ranks) leave runs of tile/256 keys whose cache lines at both ends are
+// written partially, so longer tiles write more efficiently: S_16 LRX sort
+// passes 866 ms at 4096-key tiles, 704 at 8192, 688 at 12288 (10240: 690).
+#ifndef CG_SORT_IPT64
+#define CG_SORT_IPT64 16
+#endif
+#ifndef CG_SORT_BLOCK64
+#define CG_SORT_BLOCK64 768
+#endif
 template <class K>
 struct TileOf {
-    static constexpr int ipt = sizeof(K) == 4 ? CG_SORT_IPT32 : 16;
-    static constexpr int block = sizeof(K) == 4 ? CG_SORT_BLOCK32 : kBlock;  // threads of a sort tile
+    static constexpr int ipt = sizeof(K) == 4 ? CG_SORT_IPT32 : CG_SORT_IPT64;
+    static constexpr int block = sizeof(K) == 4 ? CG_SORT_BLOCK32 : CG_SORT_BLOCK64;  // threads of a sort tile
     static constexpr int waves = block / kWave;
     static constexpr int tile = block * ipt;
     static constexpr int wave_seg = kWave * ipt;  // keys owned by one wave
     static constexpr int split = sizeof(K) == 4 ? CG_SORT_SPLIT32 : CG_SORT_SPLIT64;
     static constexpr int buf = tile / split;  // keys in the LDS reorder buffer
 };
-constexpr int kTile = TileOf<uint64_t>::tile;  // the shortest tile: sizes look-back state
+constexpr int kTile = TileOf<uint64_t>::tile;  // frontier states per tile of the fused first pass
+// the shorter of the two tiles sizes the look-back words of a pass
+constexpr int kTileMin = TileOf<uint32_t>::tile < kTile ? TileOf<uint32_t>::tile : kTile;
 #ifndef CG_EXPAND_CONTIG
 #define CG_EXPAND_CONTIG 1  // ranked-expand threads take consecutive frontier states
 #endif
@@ -375,13 +388,20 @@ __device__ __forceinline__ void with_prefix_len(int m, Fn &&fn) {
     }
 }
 
+// Rank type of S_N: 32 bits up to n = 12, 64 bits beyond (16! < 2^45).
+template <int N>
+using RankT = typename std::conditional<(N <= kRankMaxN), uint32_t, uint64_t>::type;
+
 // gfix (null: full ranks): per generator, the first position from which it
-// fixes every position (0 for the identity)
+// fixes every position (0 for the identity). Incremental ranks are built for
+// 32-bit ranks only (n <= 12).
 template <int N, bool Incr>
 __global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
     const uint64_t *__restrict__ frontier, uint64_t F, const GenSel *__restrict__ gsel,
-    const uint8_t *__restrict__ gfix, int k, uint32_t *__restrict__ out, uint64_t per_block,
+    const uint8_t *__restrict__ gfix, int k, RankT<N> *__restrict__ out, uint64_t per_block,
     unsigned long long *__restrict__ ghist) {
+    using R = RankT<N>;
+    static_assert(!Incr || N <= kRankMaxN, "incremental ranks are 32-bit");
     constexpr int kIpt = Incr ? kExpandIptIncr : kExpandIpt;
     constexpr int kP = RankPasses<N>::passes;
     // the source shifts follow the k fix positions at the next 4-byte boundary
@@ -422,16 +442,16 @@ __global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
             }
         }
         for (int g = 0; g < k; ++g) {
-            uint32_t *o = out + (uint64_t)g * F;
+            R *o = out + (uint64_t)g * F;
             auto body = [&](auto MM) {
                 constexpr int M = decltype(MM)::value;
 #pragma unroll
                 for (int j = 0; j < kIpt; ++j) {
                     const uint64_t f = base + expand_slot<kIpt>(j);
                     if (kGuard && f >= hi) continue;
-                    uint32_t r;
+                    R r;
                     if constexpr (!Incr) {
-                        r = perm_rank_t<N>(apply_gensel(st[j], gsel[g]));
+                        r = perm_rank_t<N, R>(apply_gensel(st[j], gsel[g]));
                     } else if constexpr (M <= N - 2) {
                         r = rank_prefix_from<N, M>(sk[j], gsh + (uint32_t)g * N) + suf[j][M - 2];
                     } else {
@@ -440,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
                     o[f] = r;
 #pragma unroll
                     for (int p = 0; p < kP; ++p) {
-                        const uint32_t d = (r >> (p * kRadixBits)) & RankPasses<N>::mask(p);
+                        const uint32_t d = (uint32_t)(r >> (p * kRadixBits)) & RankPasses<N>::mask(p);
                         if (p < CG_HIST_DIRECT_PASSES) {
                             atomicAdd(&s_h[p][d], 1u);
                         } else {
@@ -976,7 +996,7 @@ typename Src::Key *run_sort(const Src &first_src, uint64_t count, typename Src::
 
 int sort_passes(int bit_lo, int bit_hi) { return make_passes(bit_lo, bit_hi).passes; }
 
-uint64_t sort_status_words(uint64_t count) { return ((count + kTile - 1) / kTile) * kRadix; }
+uint64_t sort_status_words(uint64_t count) { return ((count + kTileMin - 1) / kTileMin) * kRadix; }
 
 uint64_t expand_sort_status_words(uint64_t F, int k) {
     const uint64_t a = ((F + kTile - 1) / kTile) * (uint64_t)k * kRadix;
@@ -1039,6 +1059,36 @@ uint32_t *expand_rank_sort(int n, const uint64_t *frontier, uint64_t F, const Ge
     // the identity, so the histograms are not read back (no host sync); a
     // pass that is one anyway runs as an ordinary pass.
     return run_sort(src, C, buf1, buf0, 0, rank_bits, w, false, 4.0 * (double)C, buf0, true, false);
+}
+
+uint64_t *expand_rank_sort64(int n, const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,
+                             uint64_t *buf0, uint64_t *buf1, int rank_bits, PipeWork &w) {
+    const uint64_t C = F * (uint64_t)k;
+    if (C == 0) return buf0;
+    w.ensure_status(sort_status_words(C));
+    unsigned long long *hist = w.hist.as<unsigned long long>();
+    if (w.prof) w.prof->begin(K_AUX);
+    hipLaunchKernelGGL(clear_kernel, dim3(8), dim3(256), 0, w.stream, hist, (uint32_t)(kMaxPasses * kRadix),
+                       w.tickets(), 32u);
+    CG_HIP(hipGetLastError());
+    if (w.prof) w.prof->end(K_AUX, 0, 0);
+    const uint64_t round = (uint64_t)kBlock * kExpandIpt;
+    const uint64_t rounds = (F + round - 1) / round;
+    const uint64_t blocks = rounds < 4096 ? rounds : 4096;
+    const uint64_t per_block = ((rounds + blocks - 1) / blocks) * round;
+    const uint32_t grid = (uint32_t)((F + per_block - 1) / per_block);
+    if (w.prof) w.prof->begin(K_EXPAND);
+    with_rank64_n(n, [&](auto NN) {
+        constexpr int N = decltype(NN)::value;
+        if (rank_bits != RankPasses<N>::bits()) throw Error(-1, "rank bits differ from those of n!");
+        hipLaunchKernelGGL((expand_rank_hist_kernel<N, false>), dim3(grid), dim3(kBlock), 0, w.stream, frontier, F,
+                           d_gsel, (const uint8_t *)nullptr, k, buf0, per_block, hist);
+    });
+    CG_HIP(hipGetLastError());
+    if (w.prof) w.prof->end(K_EXPAND, 8.0 * (double)F + 8.0 * (double)C, (double)C);
+    const ArraySrcT<uint64_t> src{buf0, C};
+    // as for 32-bit ranks: every pass runs, the histograms stay on the device
+    return run_sort(src, C, buf1, buf0, 0, rank_bits, w, false, 8.0 * (double)C, buf0, true, false);
 }
 
 uint64_t *expand_sort(const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,

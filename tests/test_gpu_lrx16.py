@@ -13,7 +13,8 @@ invariance when it searches generating sets up to conjugacy):
   * generators conjugated by a seeded random h,
   * a seeded random start permutation,
   * key-range chunks forced so that the largest layers split into at least
-    four chunks (each chunk regenerates its candidates from the frontier).
+    four chunks (each chunk regenerates its candidates from the frontier),
+  * candidates sorted as packed 64-bit keys instead of 64-bit ranks.
 Each must give all layer sizes of the plain run. Tolerance: none.
 """
 
@@ -108,5 +109,12 @@ def test_forced_chunks_same_growth(plain, monkeypatch):
     monkeypatch.setenv("CG_CHUNK_CANDIDATES", str(cap))
     print("S_16 LRX with chunks of at most", cap, "candidates", flush=True)
     r = _run(I.lrx(16))
+    assert r.status == N.CG_TRUNCATED
+    assert r.sizes == plain.sizes
+
+
+def test_packed_key_sort_same_growth(plain):
+    print("S_16 LRX with candidates sorted as packed keys", flush=True)
+    r = _run(I.lrx(16), packed_sort=True)
     assert r.status == N.CG_TRUNCATED
     assert r.sizes == plain.sizes

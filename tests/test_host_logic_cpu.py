@@ -81,3 +81,58 @@ def test_host_expand_selectors_match_gather(n):
     assert rc == 0
     expected = np.concatenate([pack(n, rows[:, gg]) for gg in gens])
     assert np.array_equal(out, expected)
+
+
+def _lehmer_rank(p):
+    """The lexicographic index by its definition (Lehmer code), in Python
+    integers."""
+    n = len(p)
+    return sum(sum(1 for j in range(i + 1, n) if p[j] < p[i]) * math.factorial(n - 1 - i) for i in range(n))
+
+
+@pytest.mark.parametrize("n", [13, 14, 15, 16])
+def test_rank64_sampled(n):
+    """64-bit ranks (n = 13..16) against the Lehmer code written out, with
+    the order preserved and unrank inverting them; rank 0 is the identity,
+    n! - 1 the reversal, and the neighbours of both ends of every split of
+    the Horner sum round-trip too."""
+    rng = np.random.default_rng(1000 + n)
+    perms = [list(map(int, rng.permutation(n))) for _ in range(400)]
+    perms += [list(range(n)), list(range(n))[::-1]]
+    keys = np.ascontiguousarray(pack(n, perms))
+    ranks = np.zeros(len(perms), dtype=np.uint64)
+    assert N.lib().cg_test_rank64(n, keys.ctypes.data_as(N.u64p), len(perms), ranks.ctypes.data_as(N.u64p),
+                                  0, None) == 0
+    for p, r in zip(perms, ranks):
+        assert _lehmer_rank(p) == int(r)
+    assert int(ranks[-2]) == 0 and int(ranks[-1]) == math.factorial(n) - 1
+    order = np.argsort(keys, kind="stable")
+    assert np.all(np.diff(ranks[order].astype(object)) > 0)
+    # ranks around multiples of the low radices (carries between the parts)
+    extra = []
+    for m in (720, 40320, 362880, 3628800, 479001600):
+        for q in (1, 7, 12345):
+            v = q * m
+            extra += [v - 1, v, v + 1]
+    extra = [v for v in extra if 0 <= v < math.factorial(n)]
+    rs = np.ascontiguousarray(np.concatenate([ranks, np.asarray(extra, dtype=np.uint64)]).astype(np.uint64))
+    back = np.zeros(len(rs), dtype=np.uint64)
+    assert N.lib().cg_test_unrank64(n, rs.ctypes.data_as(N.u64p), len(rs), back.ctypes.data_as(N.u64p), 0,
+                                    None) == 0
+    assert np.array_equal(back[: len(keys)], keys)
+    again = np.zeros(len(rs), dtype=np.uint64)
+    assert N.lib().cg_test_rank64(n, back.ctypes.data_as(N.u64p), len(rs), again.ctypes.data_as(N.u64p), 0,
+                                  None) == 0
+    assert np.array_equal(again, rs)
+    for v, k in zip(extra, back[len(keys):]):
+        row = [(int(k) >> (4 * (n - 1 - i))) & 15 for i in range(n)]
+        assert sorted(row) == list(range(n)) and _lehmer_rank(row) == v
+
+
+def test_rank64_rejects_bad_input():
+    r = np.zeros(1, dtype=np.uint64)
+    k = np.zeros(1, dtype=np.uint64)
+    assert N.lib().cg_test_rank64(12, k.ctypes.data_as(N.u64p), 1, r.ctypes.data_as(N.u64p), 0, None) == N.CG_E_INVAL
+    r[0] = math.factorial(13)
+    assert N.lib().cg_test_unrank64(13, r.ctypes.data_as(N.u64p), 1, k.ctypes.data_as(N.u64p), 0,
+                                    None) == N.CG_E_INVAL
