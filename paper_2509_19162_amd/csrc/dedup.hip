@@ -86,7 +86,17 @@ struct RankedRefs {
     __device__ __forceinline__ K from_layer(uint32_t x) const { return x; }
     __device__ __forceinline__ uint64_t to_layer(K x) const { return perm_unrank_t<N>(x); }
 };
-// Candidates as 64-bit ranks (n = 13..16); reference layers packed.
+// Candidates as 64-bit ranks (n = 13..16); reference layers packed, or
+// given by their 64-bit ranks (Ranked64Refs).
+template <int N>
+struct Ranked64Refs {
+    using K = uint64_t;
+    using Ref = uint64_t;
+    static constexpr bool kConvert = true;
+    int n;
+    __device__ __forceinline__ K from_layer(uint64_t x) const { return x; }
+    __device__ __forceinline__ uint64_t to_layer(K x) const { return perm_unrank_t<N, uint64_t>(x); }
+};
 template <int N>
 struct Ranked64Keys {
     using K = uint64_t;
@@ -362,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(P pol, const typename P:
                                                         const uint32_t *__restrict__ cnt,
                                                         const uint64_t *__restrict__ off, uint32_t ntiles,
                                                         uint64_t *__restrict__ out, uint64_t out_cap,
-                                                        uint32_t *__restrict__ rank_out,
+                                                        typename P::K *__restrict__ rank_out,
                                                         uint32_t *__restrict__ err) {
     using K = typename P::K;
     constexpr int kT = gather_tiles<P>();
@@ -371,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(P pol, const typename P:
     auto put = [&](uint64_t dst, K v) {
         if (dst < out_cap) {
             out[dst] = pol.to_layer(v);
-            if constexpr (sizeof(K) == 4)
+            if constexpr (P::kConvert)
                 if (rank_out) rank_out[dst] = v;
         } else {
             atomicOr(err, 4u);  // more survivors than the output holds
@@ -462,7 +472,7 @@ void dedup_count_impl(P pol, const typename P::K *sorted, uint64_t C, const type
 
 template <class P>
 void dedup_gather_impl(P pol, const typename P::K *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w,
-                       uint32_t *rank_out = nullptr) {
+                       typename P::K *rank_out = nullptr) {
     if (!w.dedup_tiles) return;
     if (w.prof) w.prof->begin(K_DEDUP);
     const uint32_t ntiles = (uint32_t)w.dedup_tiles;
@@ -483,7 +493,7 @@ void launch_dedup_count(const uint64_t *sorted, uint64_t C, const uint64_t *a, u
 }
 
 void launch_dedup_gather(const uint64_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w) {
-    dedup_gather_impl(PackedKeys{0}, tmp, out, out_cap, w);
+    dedup_gather_impl(PackedKeys{0}, tmp, out, out_cap, w, (uint64_t *)nullptr);
 }
 
 void launch_dedup_count_ranked(int n, const uint32_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,
@@ -516,9 +526,18 @@ void launch_dedup_count_ranked64(int n, const uint64_t *sorted, uint64_t C, cons
     });
 }
 
-void launch_dedup_gather_ranked64(int n, const uint64_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w) {
+void launch_dedup_gather_ranked64(int n, const uint64_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w,
+                                  uint64_t *rank_out) {
     with_rank64_n(n, [&](auto NN) {
-        dedup_gather_impl(Ranked64Keys<decltype(NN)::value>{n}, tmp, out, out_cap, w);
+        dedup_gather_impl(Ranked64Keys<decltype(NN)::value>{n}, tmp, out, out_cap, w, rank_out);
+    });
+}
+
+void launch_dedup_count_ranked64_refs(int n, const uint64_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,
+                                      const uint64_t *b, uint64_t nb, uint64_t *tmp, uint64_t *d_count,
+                                      PipeWork &w) {
+    with_rank64_n(n, [&](auto NN) {
+        dedup_count_impl(Ranked64Refs<decltype(NN)::value>{n}, sorted, C, a, na, b, nb, tmp, d_count, w);
     });
 }
 

@@ -451,10 +451,10 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
         }
     }
     const bool ranked64 = perm_any && !(spec.flags & CG_PACKED_SORT);
-    // Ranked runs keep the 32-bit ranks of layers d-1 and d beside the packed
-    // layers (written by the gather), so the set difference does not rank its
-    // reference keys again. A layer from the chunked path has none; the next
-    // two steps then rank the packed layers on the fly.
+    // Ranked runs keep the ranks (32- or 64-bit) of layers d-1 and d beside
+    // the packed layers (written by the gather), so the set difference does
+    // not rank its reference keys again. A layer from the chunked path has
+    // none; the next two steps then rank the packed layers on the fly.
     int kp = 0, kc = 1, kn = 2;
     bool rk_cur = false, rk_prev = false;
     if (ranked && !directed) {
@@ -462,6 +462,12 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
         rk_[kc].ensure(64);
         CG_HIP(hipMemcpyAsync(rk_[kc].p, &r0, sizeof r0, hipMemcpyHostToDevice, stream_));
         rk_cur = rk_prev = true;  // layer -1 is empty
+    } else if (ranked64 && !directed) {
+        uint64_t r0 = 0;
+        with_rank64_n(n, [&](auto NN) { r0 = perm_rank_t<decltype(NN)::value, uint64_t>(key0); });
+        rk_[kc].ensure(64);
+        CG_HIP(hipMemcpyAsync(rk_[kc].p, &r0, sizeof r0, hipMemcpyHostToDevice, stream_));
+        rk_cur = rk_prev = true;
     }
     int rank_bits = 0;
     while (rank_bits < 63 && (1ull << rank_bits) < spec.orbit_bound) ++rank_bits;
@@ -568,14 +574,25 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             uint64_t *c0 = cand0_.as<uint64_t>(), *c1 = cand1_.as<uint64_t>();
             const uint64_t *sorted = expand_rank_sort64(n, Ld, F, gsel_.as<GenSel>(), k, c0, c1, rank_bits, w_);
             uint64_t *scratch = sorted == c0 ? c1 : c0;
-            launch_dedup_count_ranked64(n, sorted, C, Ra, na, Rb, nb, scratch, w_.counter(), w_);
+            const bool by_rank = !directed && rk_cur && rk_prev;
+            if (by_rank)
+                launch_dedup_count_ranked64_refs(n, sorted, C, rk_[kc].as<const uint64_t>(), F,
+                                                 rk_[kp].as<const uint64_t>(), np, scratch, w_.counter(), w_);
+            else
+                launch_dedup_count_ranked64(n, sorted, C, Ra, na, Rb, nb, scratch, w_.counter(), w_);
             N = read_counter();
             if (N > C || N > room) throw Error(CG_E_DEVICE, "layer size out of range (device error)");
             if (!keep_all) {
                 lay_[in].ensure(std::max<uint64_t>(N, 1) * sizeof(uint64_t), 1.25);
                 out = lay_[in].as<uint64_t>();
             }
-            launch_dedup_gather_ranked64(n, scratch, out, keep_all ? out_cap : N, w_);
+            uint64_t *rank_out = nullptr;
+            if (!directed) {
+                rk_[kn].ensure(std::max<uint64_t>(N, 1) * sizeof(uint64_t), 1.25);
+                rank_out = rk_[kn].as<uint64_t>();
+            }
+            launch_dedup_gather_ranked64(n, scratch, out, keep_all ? out_cap : N, w_, rank_out);
+            rk_next = rank_out != nullptr;
         } else {
             const uint64_t *sorted = expand_sort(Ld, F, gsel_.as<GenSel>(), k, cand0_.as<uint64_t>(),
                                                  cand1_.as<uint64_t>(), bit_lo, bit_hi, w_);

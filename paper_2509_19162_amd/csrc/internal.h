@@ -236,7 +236,13 @@ void launch_dedup_count_ranked_refs(int n, const uint32_t *sorted, uint64_t C, c
 // written back as packed keys.
 void launch_dedup_count_ranked64(int n, const uint64_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,
                                  const uint64_t *b, uint64_t nb, uint64_t *tmp, uint64_t *d_count, PipeWork &w);
-void launch_dedup_gather_ranked64(int n, const uint64_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w);
+// rank_out (optional): the survivors' 64-bit ranks, beside the packed layer.
+void launch_dedup_gather_ranked64(int n, const uint64_t *tmp, uint64_t *out, uint64_t out_cap, PipeWork &w,
+                                  uint64_t *rank_out = nullptr);
+// The same count with the reference layers given by their 64-bit ranks.
+void launch_dedup_count_ranked64_refs(int n, const uint64_t *sorted, uint64_t C, const uint64_t *a, uint64_t na,
+                                      const uint64_t *b, uint64_t nb, uint64_t *tmp, uint64_t *d_count,
+                                      PipeWork &w);
 // Permute-expand into 32-bit ranks: out[g*F + f] = rank(key(s_f . g)).
 void launch_expand_ranked(int n, const uint64_t *frontier, uint64_t F, const GenSel *d_gsel,
                           int k, uint32_t *out, PipeWork &w);

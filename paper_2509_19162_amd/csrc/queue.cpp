@@ -55,7 +55,7 @@ uint64_t factorial_u64(int n) {
 // Upper bound of the device bytes one job can make an engine or a group
 // hold. Sort path, per candidate: two key arrays (8 B each), look-back words
 // (at most 0.5 B), kill flags (1 B); per state of a layer: three packed
-// windows (8 B) and their ranks (4 B); directed sets: the sorted visited
+// windows (8 B) and their ranks (up to 8 B); directed sets: the sorted visited
 // array twice (8 B per state). A layer holds at most min(orbit, k * F)
 // states and an expanded one at most min(orbit, max_frontier), so the
 // candidates of one step are at most k * F. Buffers may grow with 50%
@@ -71,7 +71,7 @@ uint64_t job_bound(const JobSpec &s) {
     double F = orbit;
     if (s.max_frontier) F = std::min(F, (double)s.max_frontier);
     const double L = std::min(orbit, k * F);
-    double b = k * F * 17.5 + 3.0 * 12.0 * L;
+    double b = k * F * 17.5 + 3.0 * 16.0 * L;
     if (!s.inverse_closed) b += 16.0 * orbit;
     return (uint64_t)(1.5 * b) + (64ull << 20);
 }
