@@ -329,6 +329,9 @@ def batch_leg(steps: int, warmup: int, tune: bool, n_jobs: int, cpu_budget: floa
     elapsed = sum(times)
     states = sum(r.states_expanded for r in res)
     value = len(jobs) * steps / elapsed
+    info = api.batch_info()
+    # the one small-job launch's HIP-event time (every such job reports it)
+    launch_ms = max((r.device_ms for r in res), default=0.0)
     log(f"batch: {value:.0f} jobs/s")
     # the plain one-job-at-a-time GPU path on the same jobs
     eng = api.Engine()
@@ -349,6 +352,12 @@ def batch_leg(steps: int, warmup: int, tune: bool, n_jobs: int, cpu_budget: floa
         "workload": f"{len(jobs)} jobs, n ~ U{{7..10}}, 2-4 uniform random permutations plus inverses, "
                     "full growth each (seed 19162)",
         "autotuned": bool(tune),
+        "tuning": {"classes": info["tuned_classes"], "heavy_split": info["heavy_split"],
+                   "file_entries": info["tune_file_entries"]} if tune else None,
+        "graph": {"builds": int(info["graph_builds"]), "launches": int(info["graph_launches"]),
+                  "replays": int(info["graph_launches"] - info["graph_builds"])},
+        "small_job_launch_ms": round(launch_ms, 2),
+        "host_ms_per_step": round(1000 * elapsed / steps - launch_ms, 2),
         "sequential_plain": {"jobs_per_s": round(seq_jobs_s, 2), "jobs": len(seq),
                              "states_per_s": round(seq_states / seq_dt, 1),
                              "speedup_of_batch": round(value / seq_jobs_s, 1)},
@@ -651,7 +660,7 @@ def main():
                                   "paper_context": {"s12_pancake_full_growth_s": PAPER_PANCAKE12_SECONDS,
                                                     "hardware": "Kaggle CPU (another machine; context only)"}})
         api.release_cached_memory()
-        line["batch4096"] = batch_leg(2, 1, False, 4096, min(cpu_budget, 10.0), host)
+        line["batch4096"] = batch_leg(3, 1, True, 4096, min(cpu_budget, 10.0), host)
         api.release_cached_memory()
         sv = serving_leg(DEFAULT_RUN_REQUESTS, 13, [0.9], min(cpu_budget, 10.0), host, plain=False)
         sv["note"] = (f"one rate point (0.9 x capacity) with {DEFAULT_RUN_REQUESTS} requests, to fit the "

@@ -186,10 +186,20 @@ void cg_engine_destroy(cg_engine_t *eng);
 
 /*
  * Batch options.
- *   stream         hipStream_t or NULL
- *   max_active     most jobs advanced together in one super-step (0 = auto)
- *   hbm_budget_bytes  device bytes the batch may use (0 = auto: 80% of free)
- *   tune           1 = let the autotuner choose tile and bucket sizes
+ *   stream         hipStream_t or NULL: the batch runs after the work already
+ *                  queued on it (on a stream the library keeps per device,
+ *                  so that its launch graph is replayed by later batches of
+ *                  the same shape)
+ *   max_active     most jobs advanced together in one tagged group (0 = auto)
+ *   hbm_budget_bytes  reserved (the batch splits groups that run out of
+ *                  device memory)
+ *   tune           1 = let the autotuner choose, per size class (n), the
+ *                  engine (one workgroup per job, or tagged groups), the
+ *                  workgroup size and the jobs per group, and for the batch
+ *                  the split that moves jobs far above their share of the
+ *                  work to groups; choices are timed on the batch itself
+ *                  and kept per device model in a file (CG_TUNE_CACHE, else
+ *                  $XDG_CACHE_HOME or ~/.cache, cayleygrowth_tune.txt)
  */
 typedef struct cg_batch_opts {
     void *stream;
@@ -212,6 +222,21 @@ typedef struct cg_batch_opts {
  */
 int cg_growth_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results,
                     const cg_batch_opts_t *opts);
+
+/* What cg_growth_batch keeps on the current device between calls. */
+typedef struct cg_batch_info {
+    uint64_t calls;           /* cg_growth_batch calls on this device          */
+    uint64_t graph_builds;    /* small-job launch graphs built                  */
+    uint64_t graph_launches;  /* launches of such graphs (replays: launches
+                                 minus builds)                                 */
+    int tuned_classes;        /* size classes with autotuned choices           */
+    double heavy_split;       /* tuned heavy-job split (1/x of the small-job
+                                 work; 0 = not tuned)                          */
+    int tune_file_entries;    /* choices read back from the tuning file        */
+} cg_batch_info_t;
+
+/* Fills *out for the current device. Returns CG_OK or CG_E_INVAL (NULL). */
+int cg_batch_info(cg_batch_info_t *out);
 
 /*
  * cg_growth_batch_noalloc -- cg_growth_batch for callers that cannot

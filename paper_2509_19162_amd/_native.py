@@ -87,6 +87,17 @@ class CgBatchOpts(ctypes.Structure):
     ]
 
 
+class CgBatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("calls", ctypes.c_uint64),
+        ("graph_builds", ctypes.c_uint64),
+        ("graph_launches", ctypes.c_uint64),
+        ("tuned_classes", ctypes.c_int),
+        ("heavy_split", ctypes.c_double),
+        ("tune_file_entries", ctypes.c_int),
+    ]
+
+
 class CgQueueOpts(ctypes.Structure):
     _fields_ = [
         ("hbm_budget_bytes", ctypes.c_uint64),
@@ -145,6 +156,7 @@ SIGNATURES = [
     ("cg_engine_destroy", None, [ctypes.c_void_p]),
     ("cg_growth_batch", ctypes.c_int,
      [ctypes.c_int, ctypes.POINTER(CgJob), ctypes.POINTER(CgResult), ctypes.POINTER(CgBatchOpts)]),
+    ("cg_batch_info", ctypes.c_int, [ctypes.POINTER(CgBatchInfo)]),
     ("cg_growth_batch_noalloc", ctypes.c_int,
      [ctypes.c_int, ctypes.POINTER(CgJob), ctypes.POINTER(CgResult), ctypes.c_void_p]),
     ("cg_queue_create", ctypes.c_void_p, [ctypes.POINTER(CgQueueOpts)]),

@@ -197,6 +197,70 @@ class Engine:
             pass
 
 
+def _struct_dtype(ctype) -> np.dtype:
+    """A numpy dtype with the byte layout of a ctypes structure (scalar and
+    pointer fields by name; other fields as raw bytes)."""
+    names, formats, offsets = [], [], []
+    for name, t in ctype._fields_:
+        f = getattr(ctype, name)
+        if t in (ctypes.c_int, ctypes.c_uint32):
+            fmt = np.int32 if t is ctypes.c_int else np.uint32
+        elif t in (ctypes.c_uint64,) or t is N.u8p or t is N.u64p or t is ctypes.c_void_p:
+            fmt = np.uint64
+        elif t is ctypes.c_double:
+            fmt = np.float64
+        else:
+            fmt = np.dtype((np.void, f.size))
+        names.append(name)
+        formats.append(fmt)
+        offsets.append(f.offset)
+    return np.dtype({"names": names, "formats": formats, "offsets": offsets, "itemsize": ctypes.sizeof(ctype)})
+
+
+def _batch_arrays(jobs, max_layers: int, flags: int):
+    """Job and result arrays of a batch in the C layouts, with the
+    generators and layer sizes in two contiguous buffers."""
+    m = len(jobs)
+    ns = np.fromiter((j[0] for j in jobs), dtype=np.int32, count=m)
+    g_arrays = [np.asarray(j[1], dtype=np.uint8).reshape(-1, int(j[0])) for j in jobs]
+    rows = np.fromiter((a.shape[0] for a in g_arrays), dtype=np.int32, count=m)
+    gens = np.ascontiguousarray(np.concatenate([a.ravel() for a in g_arrays])) if m else np.zeros(1, np.uint8)
+    goff = np.zeros(m, dtype=np.uint64)
+    if m > 1:
+        goff[1:] = np.cumsum((rows.astype(np.uint64) * ns.astype(np.uint64))[:-1])
+    mf = np.fromiter(((j[2] or 0) if len(j) > 2 else 0 for j in jobs), dtype=np.uint64, count=m)
+    ml = np.fromiter(((j[3] or max_layers) if len(j) > 3 else max_layers for j in jobs), dtype=np.int32, count=m)
+    soff = np.zeros(m, dtype=np.uint64)
+    if m > 1:
+        soff[1:] = np.cumsum(ml[:-1].astype(np.uint64))
+    sizes = np.zeros(max(int(ml.sum()), 1), dtype=np.uint64)
+    ja = np.zeros(m, dtype=_struct_dtype(N.CgJob))
+    ja["n"] = ns
+    ja["gens"] = np.uint64(gens.ctypes.data) + goff
+    ja["n_gens"] = rows
+    ja["max_layers"] = ml
+    ja["max_frontier"] = mf
+    ja["flags"] = flags
+    ra = np.zeros(m, dtype=_struct_dtype(N.CgResult))
+    ra["layer_sizes"] = np.uint64(sizes.ctypes.data) + soff * np.uint64(8)
+    return ja, ra, gens, sizes, soff
+
+
+def _batch_results(ra, sizes, soff) -> List[GrowthResult]:
+    out = []
+    status = ra["status"].tolist()
+    nl = ra["num_layers"].tolist()
+    se = ra["states_expanded"].tolist()
+    ca = ra["candidates"].tolist()
+    dm = ra["device_ms"].tolist()
+    ts, tad, td = ra["t_submit"].tolist(), ra["t_admit"].tolist(), ra["t_done"].tolist()
+    so = soff.tolist()
+    for i in range(len(status)):
+        sz = sizes[so[i]: so[i] + nl[i]].tolist() if status[i] >= 0 else []
+        out.append(GrowthResult(status[i], sz, se[i], ca[i], dm[i], ts[i], tad[i], td[i], {}, None))
+    return out
+
+
 def growth_batch(jobs, max_layers: int = 256, max_active: int = 0, budget_bytes: int = 0,
                  tune: bool = False, stream=None, allow_directed: bool = False) -> List[GrowthResult]:
     """Many independent jobs in shared super-steps (``cg_growth_batch``).
@@ -205,25 +269,21 @@ def growth_batch(jobs, max_layers: int = 256, max_active: int = 0, budget_bytes:
     ``(n, gens, max_frontier, max_layers)``. Per-job failures (a bad
     generator row) show up as a negative ``status`` in that job's result.
     """
-    holders = []
-    for j in jobs:
-        n, gens = j[0], j[1]
-        mf = j[2] if len(j) > 2 else None
-        ml = j[3] if len(j) > 3 and j[3] else max_layers
-        holders.append(_JobHolder(n, gens, ml, mf, N.CG_ALLOW_DIRECTED if allow_directed else 0, None, 0))
-    JobArr = N.CgJob * len(holders)
-    ResArr = N.CgResult * len(holders)
-    ja = JobArr(*[h.job for h in holders])
-    ra = ResArr()
-    for i, h in enumerate(holders):
-        ra[i].layer_sizes = h.sizes.ctypes.data_as(N.u64p)
+    ja, ra, gens, sizes, soff = _batch_arrays(jobs, max_layers, N.CG_ALLOW_DIRECTED if allow_directed else 0)
     opts = N.CgBatchOpts(_stream_handle(stream), max_active, budget_bytes, 1 if tune else 0)
-    _check(N.lib().cg_growth_batch(len(holders), ja, ra, ctypes.byref(opts)))
-    out = []
-    for i, h in enumerate(holders):
-        h.res = ra[i]
-        out.append(h.result())
-    return out
+    _check(N.lib().cg_growth_batch(len(jobs), ja.ctypes.data_as(ctypes.POINTER(N.CgJob)),
+                                   ra.ctypes.data_as(ctypes.POINTER(N.CgResult)), ctypes.byref(opts)))
+    return _batch_results(ra, sizes, soff)
+
+
+def batch_info() -> Dict[str, float]:
+    """What ``cg_growth_batch`` keeps on the current device (``cg_batch_info``):
+    calls, launch graphs built and launched (replays = launches - builds),
+    autotuned classes, the tuned heavy-job split, entries read from the
+    tuning file."""
+    st = N.CgBatchInfo()
+    _check(N.lib().cg_batch_info(ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in N.CgBatchInfo._fields_}
 
 
 def growth_batch_noalloc(jobs, max_layers: int = 256, stream=None,
@@ -231,22 +291,10 @@ def growth_batch_noalloc(jobs, max_layers: int = 256, stream=None,
     """``cg_growth_batch_noalloc``: the jobs of ``growth_batch`` (each with
     n <= 10) run without any device allocation, on the library's static
     device array. Same job tuple forms as ``growth_batch``."""
-    holders = []
-    for j in jobs:
-        n, gens = j[0], j[1]
-        mf = j[2] if len(j) > 2 else None
-        ml = j[3] if len(j) > 3 and j[3] else max_layers
-        holders.append(_JobHolder(n, gens, ml, mf, N.CG_ALLOW_DIRECTED if allow_directed else 0, None, 0))
-    ja = (N.CgJob * len(holders))(*[h.job for h in holders])
-    ra = (N.CgResult * len(holders))()
-    for i, h in enumerate(holders):
-        ra[i].layer_sizes = h.sizes.ctypes.data_as(N.u64p)
-    _check(N.lib().cg_growth_batch_noalloc(len(holders), ja, ra, _stream_handle(stream)))
-    out = []
-    for i, h in enumerate(holders):
-        h.res = ra[i]
-        out.append(h.result())
-    return out
+    ja, ra, gens, sizes, soff = _batch_arrays(jobs, max_layers, N.CG_ALLOW_DIRECTED if allow_directed else 0)
+    _check(N.lib().cg_growth_batch_noalloc(len(jobs), ja.ctypes.data_as(ctypes.POINTER(N.CgJob)),
+                                           ra.ctypes.data_as(ctypes.POINTER(N.CgResult)), _stream_handle(stream)))
+    return _batch_results(ra, sizes, soff)
 
 
 def release_cached_memory() -> None:

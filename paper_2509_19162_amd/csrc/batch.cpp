@@ -19,6 +19,8 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
+#include <string>
 
 namespace cg {
 
@@ -272,11 +274,19 @@ namespace cg {
 
 // Size classes of a batch are the job's n. Per class the batch picks an
 // engine: the small-job engine (one workgroup per job, every such job of
-// the batch in one persistent launch captured as a hipGraph) or tagged
-// super-step groups of at most `cap` jobs. The default: small-job engine up
-// to n = wg_max_n (CG_WG_MAX_N, default 10); with opts->tune the autotuner
-// times both engines on a sample of each class and keeps the faster, and
-// picks the workgroup size. Results are exact either way.
+// the batch in one persistent launch, built as a hipGraph that replays while
+// the batch's shape repeats) or tagged super-step groups of at most `cap`
+// jobs. A job far above its share of the small-job work leaves that engine
+// for a group (one workgroup would run it long after the rest finished).
+// Defaults: small-job engine up to n = wg_max_n (CG_WG_MAX_N, default 10),
+// workgroup size by n, groups of up to 4096 jobs, the heavy-job split at
+// 1/64 of the small-job work. With opts->tune the autotuner times the
+// choices on the batch itself: per class, both engines, three workgroup
+// sizes and two group sizes on a sample of up to 256 jobs; for the whole
+// batch, three heavy-job splits. Its choices are kept per device model in
+// a file (CG_TUNE_CACHE, default $XDG_CACHE_HOME or ~/.cache, then
+// cayleygrowth_tune.txt) and reused by later batches and processes.
+// Results are exact whatever is chosen.
 namespace {
 
 int default_wg_max_n() {
@@ -286,32 +296,126 @@ int default_wg_max_n() {
 }
 
 struct ClassChoice {
-    bool wg = false;
-    WgTuning tuning;
+    bool wg = true;        // small-job engine (else tagged groups)
+    int block = 256;       // its workgroup size
+    int group_cap = 4096;  // jobs per tagged group
 };
 
-double time_groups(std::vector<std::pair<JobSpec, cg_result_t *>> &sample, int n, hipStream_t stream) {
+// What a cg_growth_batch call keeps on a device between calls: a stream,
+// the small-job runner (so its launch graph replays while the shape
+// repeats) and the autotuner's choices.
+struct BatchContext {
+    std::mutex mu;
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    std::unique_ptr<WgRunner> runner;
+    std::string model;                 // device model the choices belong to
+    std::map<int, ClassChoice> tuned;  // by n
+    double heavy_div = 0;              // 0: not tuned
+    bool loaded = false;
+    uint64_t calls = 0;
+    int file_entries = 0;
+};
+
+BatchContext &batch_context(int dev) {
+    static std::mutex mu;
+    static std::map<int, BatchContext *> ctx;  // never destroyed: their streams live until exit
+    std::lock_guard<std::mutex> lk(mu);
+    BatchContext *&c = ctx[dev];
+    if (!c) {
+        c = new BatchContext();
+        c->dev = dev;
+        hipDeviceProp_t prop{};
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            c->model = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+        else
+            c->model = "unknown";
+        for (char &ch : c->model)
+            if (ch == ' ' || ch == '\n') ch = '_';
+    }
+    return *c;
+}
+
+std::string tune_cache_path() {
+    if (const char *e = std::getenv("CG_TUNE_CACHE")) return e;
+    std::string dir;
+    if (const char *x = std::getenv("XDG_CACHE_HOME"))
+        dir = x;
+    else if (const char *h = std::getenv("HOME"))
+        dir = std::string(h) + "/.cache";
+    else
+        return "";
+    return dir + "/cayleygrowth_tune.txt";
+}
+
+// File format, one choice per line: "<model> class <n> <wg> <block> <cap>"
+// or "<model> heavy <divisor>"; the last line for a key wins.
+void load_tuning(BatchContext &c) {
+    c.loaded = true;
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return;
+    char model[128], kind[16];
+    while (std::fscanf(f, "%127s %15s", model, kind) == 2) {
+        if (c.model != model) {
+            int ch;
+            while ((ch = std::fgetc(f)) != EOF && ch != '\n') {
+            }
+            continue;
+        }
+        if (std::strcmp(kind, "class") == 0) {
+            int n, wg, block, cap;
+            if (std::fscanf(f, "%d %d %d %d", &n, &wg, &block, &cap) != 4) break;
+            if (n < 1 || n > 16 || block < 64 || block > 1024 || block % 64 || cap < 1) continue;
+            c.tuned[n] = ClassChoice{wg != 0, block, cap};
+            ++c.file_entries;
+        } else if (std::strcmp(kind, "heavy") == 0) {
+            double d;
+            if (std::fscanf(f, "%lf", &d) != 1) break;
+            if (d >= 1) {
+                c.heavy_div = d;
+                ++c.file_entries;
+            }
+        }
+    }
+    std::fclose(f);
+}
+
+void save_tuning(const BatchContext &c) {
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    FILE *f = std::fopen(path.c_str(), "a");
+    if (!f) return;  // an unwritable cache only costs a re-tune
+    for (auto &kv : c.tuned)
+        std::fprintf(f, "%s class %d %d %d %d\n", c.model.c_str(), kv.first, kv.second.wg ? 1 : 0, kv.second.block,
+                     kv.second.group_cap);
+    if (c.heavy_div > 0) std::fprintf(f, "%s heavy %g\n", c.model.c_str(), c.heavy_div);
+    std::fclose(f);
+}
+
+double time_groups(std::vector<std::pair<JobSpec, cg_result_t *>> &sample, int n, int cap, hipStream_t stream) {
     const double t = now_seconds();
-    BatchGroup g(stream, n, (int)sample.size());
-    for (int j = 0; j < (int)sample.size(); ++j) g.add(j, sample[j].first, sample[j].second, t, t);
-    std::vector<int> fin;
-    while (!g.idle()) g.step(fin);
+    for (size_t base = 0; base < sample.size(); base += (size_t)cap) {
+        const int m = (int)std::min<size_t>((size_t)cap, sample.size() - base);
+        BatchGroup g(stream, n, m);
+        for (int j = 0; j < m; ++j) g.add(j, sample[base + j].first, sample[base + j].second, t, t);
+        std::vector<int> fin;
+        while (!g.idle()) g.step(fin);
+    }
     CG_HIP(hipStreamSynchronize(stream));
     return now_seconds() - t;
 }
 
-// Times both engines on up to 256 jobs of the class (cached per device and
-// n for the process).
-ClassChoice tune_class(int n, std::vector<std::pair<JobSpec, cg_result_t *>> &items, hipStream_t stream) {
-    static std::mutex mu;
-    static std::map<std::pair<int, int>, ClassChoice> cache;
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        auto f = cache.find({dev, n});
-        if (f != cache.end()) return f->second;
-    }
+int group_cap_for(int n) {
+    int cap = 1;
+    while (4 * n + 1 + (int)std::log2((double)cap) <= 64 && cap < 4096) cap <<= 1;
+    if (4 * n >= 64) cap = 1;
+    return cap;
+}
+
+// Times the choices for one class on up to 256 of its jobs.
+ClassChoice tune_class(int n, std::vector<std::pair<JobSpec, cg_result_t *>> &items, BatchContext &c) {
     const size_t m = std::min<size_t>(256, items.size());
     std::vector<std::pair<JobSpec, cg_result_t *>> sample;
     std::vector<std::vector<uint64_t>> sizes(m);
@@ -324,38 +428,153 @@ ClassChoice tune_class(int n, std::vector<std::pair<JobSpec, cg_result_t *>> &it
     }
     std::vector<WgItem> wi;
     for (auto &x : sample) wi.push_back({&x.first, x.second});
-    ClassChoice c;
-    c.tuning = tune_wg(wi, stream);
-    WgRunner r(stream);
-    r.run(wi, c.tuning, now_seconds());
-    double t = now_seconds();
-    r.run(wi, c.tuning, t);
-    const double wg_s = now_seconds() - t;
-    (void)time_groups(sample, n, stream);  // warm-up (allocations)
-    const double grp_s = time_groups(sample, n, stream);
-    c.wg = wg_s <= grp_s;
+    ClassChoice ch;
+    double t0 = now_seconds();
+    double dev_ms = 0;
+    ch.block = tune_wg(wi, *c.runner, &dev_ms).block;
+    WgTuning t;
+    t.block = ch.block;
+    t0 = now_seconds();
+    c.runner->run(wi, t, t0);
+    const double wg_s = now_seconds() - t0;
+    double grp_s = -1;
+    const int cap_max = group_cap_for(n);
+    for (int cap : {std::min(512, cap_max), cap_max}) {
+        (void)time_groups(sample, n, cap, c.stream);  // warm-up (allocations)
+        const double g = time_groups(sample, n, cap, c.stream);
+        if (grp_s < 0 || g < grp_s) {
+            grp_s = g;
+            ch.group_cap = cap;
+        }
+    }
+    ch.wg = wg_s <= grp_s;
     if (std::getenv("CG_TUNE_LOG"))
-        std::fprintf(stderr, "[tune] n=%d sample=%zu workgroup=%d wg %.2f ms, groups %.2f ms -> %s\n", n, m,
-                     c.tuning.block, 1e3 * wg_s, 1e3 * grp_s, c.wg ? "workgroups" : "groups");
-    std::lock_guard<std::mutex> lk(mu);
-    cache[{dev, n}] = c;
-    return c;
+        std::fprintf(stderr, "[tune] n=%d sample=%zu workgroup=%d wg %.2f ms, groups(cap %d) %.2f ms -> %s\n", n, m,
+                     ch.block, 1e3 * wg_s, ch.group_cap, 1e3 * grp_s, ch.wg ? "workgroups" : "groups");
+    return ch;
+}
+
+struct Item {
+    int idx;
+    JobSpec spec;
+};
+
+uint64_t job_work(const JobSpec &sp) {
+    uint64_t w = (uint64_t)std::max(1, sp.k);
+    for (int i = 2; i <= sp.n; ++i) w *= (uint64_t)i;
+    return w;
+}
+
+// One batch with the given choices (classes without a tuned entry take the
+// defaults). Returns the seconds it took.
+double run_with(std::map<int, std::vector<Item>> &by_n, cg_result_t *results, const cg_batch_opts_t *opts,
+                BatchContext &c, bool use_tuned, double heavy_div, double t0) {
+    const double ts = now_seconds();
+    hipStream_t stream = c.stream;
+    const int wg_max_n = default_wg_max_n();
+    double wg_total = 0;
+    for (auto &kv : by_n)
+        for (auto &it : kv.second)
+            if (wg_eligible(it.spec)) wg_total += (double)job_work(it.spec);
+    const double heavy = std::max((double)(1ull << 22), wg_total / heavy_div);
+    std::vector<WgItem> wg_items;
+    std::vector<Item *> alone;
+    WgTuning wg_t;
+    int wg_t_n = -1;
+    for (auto &kv : by_n) {
+        const int n = kv.first;
+        auto &all = kv.second;
+        ClassChoice ch;
+        ch.wg = n <= wg_max_n;
+        ch.block = n >= 10 ? 1024 : (n == 9 ? 512 : 256);  // the autotuner's usual picks on MI355X
+        ch.group_cap = group_cap_for(n);
+        if (use_tuned) {
+            auto f = c.tuned.find(n);
+            if (f != c.tuned.end()) ch = f->second;
+        }
+        std::vector<Item> items;
+        for (auto &it : all) {
+            const bool heavy_job = (double)job_work(it.spec) > heavy;
+            if (wg_eligible(it.spec) && (!it.spec.inverse_closed || (ch.wg && !heavy_job))) {
+                wg_items.push_back({&it.spec, &results[it.idx]});
+                if (n > wg_t_n) {
+                    wg_t_n = n;
+                    wg_t.block = ch.block;
+                }
+            } else if (!it.spec.inverse_closed) {
+                alone.push_back(&it);  // groups subtract two layers only
+            } else {
+                items.push_back(it);
+            }
+        }
+        if (items.empty()) continue;
+        int cap = std::min(ch.group_cap, group_cap_for(n));
+        if (opts && opts->max_active > 0) cap = std::min(cap, opts->max_active);
+        // groups of at most `cap` jobs; a group that runs out of device
+        // memory is split in half and its jobs start over
+        std::vector<std::pair<size_t, size_t>> todo;
+        for (size_t base = 0; base < items.size(); base += (size_t)cap)
+            todo.push_back({base, std::min<size_t>((size_t)cap, items.size() - base)});
+        while (!todo.empty()) {
+            const auto span = todo.back();
+            todo.pop_back();
+            const int m = (int)span.second;
+            try {
+                BatchGroup g(stream, n, m);
+                for (int j = 0; j < m; ++j) {
+                    Item &it = items[span.first + j];
+                    g.add(j, it.spec, &results[it.idx], t0, now_seconds());
+                }
+                std::vector<int> fin;
+                while (!g.idle()) g.step(fin);
+            } catch (const Error &e) {
+                if (e.code != CG_E_NOMEM || m == 1) throw;
+                CG_HIP(hipStreamSynchronize(stream));
+                todo.push_back({span.first + (size_t)m / 2, (size_t)(m - m / 2)});
+                todo.push_back({span.first, (size_t)m / 2});
+            }
+        }
+    }
+    if (!alone.empty()) {
+        // directed jobs the small-job engine cannot take: one engine, one
+        // job after the other (every visited state subtracted)
+        Engine eng(stream);
+        for (Item *it : alone) {
+            cg_result_t *r = &results[it->idx];
+            try {
+                eng.run(it->spec, r);
+            } catch (const Error &e) {
+                r->status = e.code;
+                r->num_layers = 0;
+            }
+        }
+    }
+    if (const char *e = std::getenv("CG_WG_BLOCK")) wg_t.block = std::atoi(e);
+    if (!wg_items.empty()) c.runner->run(wg_items, wg_t, t0);  // one persistent launch for every small job
+    CG_HIP(hipStreamSynchronize(stream));
+    return now_seconds() - ts;
 }
 
 }  // namespace
 
 void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_batch_opts_t *opts) {
     const double t0 = now_seconds();
-    hipStream_t stream = opts ? (hipStream_t)opts->stream : nullptr;
-    bool own = false;
-    if (!stream) {
-        CG_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
-        own = true;
+    int dev = 0;
+    CG_HIP(hipGetDevice(&dev));
+    BatchContext &c = batch_context(dev);
+    std::lock_guard<std::mutex> lk(c.mu);  // one batch at a time per device
+    if (!c.stream) CG_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+    if (!c.runner) c.runner.reset(new WgRunner(c.stream));
+    ++c.calls;
+    // work already queued on the caller's stream comes first
+    hipStream_t user = opts ? (hipStream_t)opts->stream : nullptr;
+    if (user) {
+        hipEvent_t e;
+        CG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        CG_HIP(hipEventRecord(e, user));
+        CG_HIP(hipStreamWaitEvent(c.stream, e, 0));
+        (void)hipEventDestroy(e);
     }
-    struct Item {
-        int idx;
-        JobSpec spec;
-    };
     std::map<int, std::vector<Item>> by_n;
     for (int i = 0; i < n_jobs; ++i) {
         cg_result_t *r = &results[i];
@@ -372,131 +591,56 @@ void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_
         }
     }
     const bool tune = opts && opts->tune;
-    const int wg_max_n = default_wg_max_n();
-    // One workgroup runs a whole job, so a job far larger than its share of
-    // the launch would leave the rest of the device idle at the end: such
-    // jobs (work n! * k above 1/64 of all small-job work, and above 2^22)
-    // go to tagged groups, which spread one job over the whole device.
-    auto work = [](const JobSpec &sp) {
-        uint64_t w = (uint64_t)std::max(1, sp.k);
-        for (int i = 2; i <= sp.n; ++i) w *= (uint64_t)i;
-        return w;
-    };
-    double wg_total = 0;
-    for (auto &kv : by_n)
-        for (auto &it : kv.second)
-            if (wg_eligible(it.spec)) wg_total += (double)work(it.spec);
-    const double heavy = std::max((double)(1ull << 22), wg_total / 64.0);
-    try {
-        std::vector<WgItem> wg_items;
-        std::vector<Item *> alone;
-        WgTuning wg_t;
-        int wg_t_n = -1;
-        for (auto &kv : by_n) {
-            const int n = kv.first;
-            auto &all = kv.second;
-            // jobs the small-job engine cannot take stay in groups; groups
-            // need closure under inverses
-            std::vector<Item> items;
-            std::vector<Item *> wg_ok;
-            for (auto &it : all) {
-                if (wg_eligible(it.spec) && (!it.spec.inverse_closed || (double)work(it.spec) <= heavy))
-                    wg_ok.push_back(&it);
-                else if (!it.spec.inverse_closed)
-                    alone.push_back(&it);  // groups subtract two layers only
-                else
-                    items.push_back(it);
-            }
-            if (!wg_ok.empty()) {
-                ClassChoice c;
-                c.wg = n <= wg_max_n;
-                bool all_closed = true;
-                for (Item *it : wg_ok) all_closed = all_closed && it->spec.inverse_closed;
-                if (tune && all_closed) {
-                    std::vector<std::pair<JobSpec, cg_result_t *>> cls;
-                    for (Item *it : wg_ok) cls.push_back({it->spec, &results[it->idx]});
-                    c = tune_class(n, cls, stream);
-                }
-                if (!all_closed) c.wg = true;  // only this engine takes directed sets
-                for (Item *it : wg_ok) {
-                    if (c.wg) {
-                        wg_items.push_back({&it->spec, &results[it->idx]});
-                        if (n > wg_t_n) {
-                            wg_t_n = n;
-                            // untuned: the shape the autotuner picks on MI355X
-                            // (jobs with bitmaps in device memory want more
-                            // threads per job)
-                            if (tune)
-                                wg_t = c.tuning;
-                            else
-                                wg_t.block = n >= 10 ? 1024 : (n == 9 ? 512 : 256);
-                        }
-                    } else if (it->spec.inverse_closed) {
-                        items.push_back(*it);
-                    }
-                }
-            }
-            if (items.empty()) continue;
-            int cap = 1;
-            while (4 * n + 1 + (int)std::log2((double)cap) <= 64 && cap < 4096) cap <<= 1;
-            if (4 * n >= 64) cap = 1;
-            if (opts && opts->max_active > 0) cap = std::min(cap, opts->max_active);
-            // groups of at most `cap` jobs; a group that runs out of device
-            // memory is split in half and its jobs start over
-            std::vector<std::pair<size_t, size_t>> todo;
-            for (size_t base = 0; base < items.size(); base += cap)
-                todo.push_back({base, std::min<size_t>(cap, items.size() - base)});
-            while (!todo.empty()) {
-                const auto span = todo.back();
-                todo.pop_back();
-                const int m = (int)span.second;
-                try {
-                    BatchGroup g(stream, n, m);
-                    for (int j = 0; j < m; ++j) {
-                        Item &it = items[span.first + j];
-                        g.add(j, it.spec, &results[it.idx], t0, now_seconds());
-                    }
-                    std::vector<int> fin;
-                    while (!g.idle()) g.step(fin);
-                } catch (const Error &e) {
-                    if (e.code != CG_E_NOMEM || m == 1) throw;
-                    CG_HIP(hipStreamSynchronize(stream));
-                    todo.push_back({span.first + (size_t)m / 2, (size_t)(m - m / 2)});
-                    todo.push_back({span.first, (size_t)m / 2});
-                }
-            }
-        }
-        if (!alone.empty()) {
-            // directed jobs the small-job engine cannot take: one engine,
-            // one job after the other (every visited state subtracted)
-            Engine eng(stream);
-            for (Item *it : alone) {
-                cg_result_t *r = &results[it->idx];
-                try {
-                    eng.run(it->spec, r);
-                } catch (const Error &e) {
-                    r->status = e.code;
-                    r->num_layers = 0;
-                }
-            }
-        }
-        if (const char *e = std::getenv("CG_WG_BLOCK")) wg_t.block = std::atoi(e);
-        if (!wg_items.empty()) {
-            // one persistent launch for every small job of the batch
-            WgRunner r(stream);
-            r.run(wg_items, wg_t, t0);
-        }
-    } catch (...) {
-        if (own) {
-            (void)hipStreamSynchronize(stream);
-            (void)hipStreamDestroy(stream);
-        }
-        throw;
+    if (!tune) {
+        (void)run_with(by_n, results, opts, c, false, 64.0, t0);
+        return;
     }
-    if (own) {
-        (void)hipStreamSynchronize(stream);
-        (void)hipStreamDestroy(stream);
+    if (!c.loaded) load_tuning(c);
+    bool changed = false;
+    for (auto &kv : by_n) {
+        const int n = kv.first;
+        if (c.tuned.count(n)) continue;
+        std::vector<std::pair<JobSpec, cg_result_t *>> cls;
+        bool wg_all = true;
+        for (auto &it : kv.second) {
+            if (!wg_eligible(it.spec) || !it.spec.inverse_closed) wg_all = false;
+            cls.push_back({it.spec, &results[it.idx]});
+        }
+        if (!wg_all || n > default_wg_max_n()) continue;  // the defaults are the only choice
+        c.tuned[n] = tune_class(n, cls, c);
+        changed = true;
     }
+    if (c.heavy_div <= 0) {
+        // the heavy-job split: each candidate on the whole batch
+        double best = -1;
+        for (double d : {16.0, 64.0, 256.0}) {
+            const double s = run_with(by_n, results, opts, c, true, d, t0);
+            if (std::getenv("CG_TUNE_LOG")) std::fprintf(stderr, "[tune] heavy split 1/%g: %.2f ms\n", d, 1e3 * s);
+            if (best < 0 || s < best) {
+                best = s;
+                c.heavy_div = d;
+            }
+        }
+        changed = true;
+    }
+    if (changed) save_tuning(c);
+    (void)run_with(by_n, results, opts, c, true, c.heavy_div, t0);
+}
+
+void batch_info(cg_batch_info_t *out) {
+    int dev = 0;
+    CG_HIP(hipGetDevice(&dev));
+    BatchContext &c = batch_context(dev);
+    std::lock_guard<std::mutex> lk(c.mu);
+    std::memset(out, 0, sizeof *out);
+    out->calls = c.calls;
+    if (c.runner) {
+        out->graph_builds = (uint64_t)c.runner->graph_captures();
+        out->graph_launches = (uint64_t)c.runner->graph_launches();
+    }
+    out->tuned_classes = (int)c.tuned.size();
+    out->heavy_split = c.heavy_div;
+    out->tune_file_entries = c.file_entries;
 }
 
 }  // namespace cg

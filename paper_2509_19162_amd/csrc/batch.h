@@ -88,5 +88,7 @@ private:
 
 // cg_growth_batch: groups by n (a size class), at most 2^tag_bits jobs each.
 void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_batch_opts_t *opts);
+// cg_batch_info for the current device.
+void batch_info(cg_batch_info_t *out);
 
 }  // namespace cg

@@ -72,9 +72,9 @@ private:
     int graph_launches_ = 0, graph_captures_ = 0;
 };
 
-// Picks the small-job launch shape for jobs like `sample` by timing the
-// candidates on it (cached per device and n class for the process).
-WgTuning tune_wg(std::vector<WgItem> &sample, hipStream_t s);
+// Picks the small-job workgroup size for jobs like `sample` by timing each
+// candidate size on it with runner `r` (its device time to *best_ms_out).
+WgTuning tune_wg(std::vector<WgItem> &sample, WgRunner &r, double *best_ms_out = nullptr);
 
 // cg_growth_batch_noalloc: the small-job engine on the library's static
 // device array (no allocation). Limits per call: jobs, distinct generator

@@ -599,33 +599,20 @@ double WgRunner::run(std::vector<WgItem> &items, const WgTuning &t, double t_sub
     return ms;
 }
 
-WgTuning tune_wg(std::vector<WgItem> &sample, hipStream_t s) {
-    static std::mutex mu;
-    static std::map<std::pair<int, int>, WgTuning> cache;
-    int n_max = 0;
-    for (auto &it : sample) n_max = std::max(n_max, it.spec->n);
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        auto f = cache.find({dev, n_max});
-        if (f != cache.end()) return f->second;
-    }
+WgTuning tune_wg(std::vector<WgItem> &sample, WgRunner &r, double *best_ms_out) {
     WgTuning best;
     double best_ms = -1;
-    WgRunner r(s);
     for (int block : {256, 512, 1024}) {
         WgTuning t;
         t.block = block;
-        r.run(sample, t, now_seconds());  // first run: capture + warm caches
+        r.run(sample, t, now_seconds());  // first run: graph build, warm caches
         const double ms = r.run(sample, t, now_seconds());
         if (best_ms < 0 || ms < best_ms) {
             best_ms = ms;
             best = t;
         }
     }
-    std::lock_guard<std::mutex> lk(mu);
-    cache[{dev, n_max}] = best;
+    if (best_ms_out) *best_ms_out = best_ms;
     return best;
 }
 

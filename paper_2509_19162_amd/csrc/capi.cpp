@@ -119,6 +119,14 @@ int cg_growth_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, cons
     });
 }
 
+int cg_batch_info(cg_batch_info_t *out) {
+    return guarded([&]() -> int {
+        if (!out) throw cg::Error(CG_E_INVAL, "NULL batch info");
+        cg::batch_info(out);
+        return CG_OK;
+    });
+}
+
 int cg_growth_batch_noalloc(int n_jobs, const cg_job_t *jobs, cg_result_t *results, void *stream) {
     return guarded([&]() -> int {
         if (n_jobs < 0 || (n_jobs > 0 && (!jobs || !results)))

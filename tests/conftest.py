@@ -12,6 +12,12 @@ except ImportError:  # the CPU suite runs without it
     torch = None
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# the batch autotuner keeps its choices in a file: tests use one of their own
+if "CG_TUNE_CACHE" not in os.environ:
+    import tempfile
+
+    os.environ["CG_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="cg_tune_"), "tune.txt")
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 

@@ -101,3 +101,45 @@ def test_batch_few_heavy_jobs_and_many_light(oracle_c):
     res = api.growth_batch(jobs, max_layers=512)
     for (n, gens), r in zip(jobs, res):
         assert r.sizes == oracle_c.growth(n, gens, max_layers=512)[0]
+
+
+def test_batch_graph_replays_across_calls(oracle_c):
+    """Repeated batches of one shape replay the small-job launch graph that
+    the first one built, with the same results."""
+    jobs = mixed_jobs(64, 7, 5, 9)
+    first = api.growth_batch(jobs, max_layers=512)
+    before = api.batch_info()
+    again = [api.growth_batch(jobs, max_layers=512) for _ in range(3)]
+    after = api.batch_info()
+    assert after["calls"] == before["calls"] + 3
+    assert after["graph_launches"] == before["graph_launches"] + 3
+    assert after["graph_builds"] == before["graph_builds"]  # all three replayed
+    for res in [first] + again:
+        for (n, gens), r in zip(jobs, res):
+            assert r.sizes == oracle_c.growth(n, gens, max_layers=512)[0]
+
+
+def test_batch_autotuner_choices_are_kept_and_exact(oracle_c, tmp_path, monkeypatch):
+    """The autotuner times engines, workgroup sizes, group sizes and the
+    heavy-job split on the batch; its choices go to the tuning file and
+    every result stays exact."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("CG_TUNE_CACHE", str(path))
+    jobs = I.batch_jobs(4096)[:600]
+    res = api.growth_batch(jobs, max_layers=512, tune=True)
+    exp = _stored_batch()
+    for i, r in enumerate(res):
+        assert r.sizes == exp[i], i
+    info = api.batch_info()
+    assert info["tuned_classes"] >= 1 and info["heavy_split"] in (16.0, 64.0, 256.0)
+    lines = path.read_text().split("\n")
+    assert any(" class " in ln for ln in lines) and any(" heavy " in ln for ln in lines)
+    res2 = api.growth_batch(jobs, max_layers=512, tune=True)  # the kept choices, no re-tuning
+    assert [r.sizes for r in res2] == [r.sizes for r in res]
+
+
+def _stored_batch():
+    path = os.path.join(GOLDEN, "oracle_growth.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle fixtures not generated")
+    return json.load(open(path))["batch_4096"]["sizes"]
