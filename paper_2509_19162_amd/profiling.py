@@ -13,6 +13,11 @@ Three commands, all reading CSV files that rocprofv3 wrote:
   a reader can tell when the figure went stale.
 * ``counters``: the same scaled FETCH/WRITE bytes for every kernel of a run,
   as a markdown table.
+* ``sq``: SQ counters per kernel (VALU and LDS instructions, LDS active and
+  bank-conflict cycles) with each kernel's average duration from a kernel
+  trace of the same command, and its VALU fraction: wave-level VALU
+  instructions over what 256 CUs issue at 2.4 GHz (one wave instruction per
+  CU per cycle: four SIMD16 units, four cycles per wave64 instruction).
 
     python -m paper_2509_19162_amd.profiling stats --csv run_kernel_stats.csv \\
         --command "rocprofv3 ..." --out profiles/x.md
@@ -165,6 +170,49 @@ def cmd_counters(a) -> None:
         f.write("\n".join(out) + "\n")
 
 
+PEAK_WAVE_INSTR_PER_S = 256 * 2.4e9  # MI355X: one VALU wave instruction per CU per cycle
+
+
+def cmd_sq(a) -> None:
+    per: Dict[str, Dict[str, Dict[str, float]]] = {}
+    for r in _rows(a.csv):
+        name = r["Kernel_Name"].replace("cg::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        d = per.setdefault(name, {}).setdefault(r["Dispatch_Id"], {})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    dur: Dict[str, List[float]] = {}
+    for r in _rows(a.trace):
+        name = r["Kernel_Name"].replace("cg::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        dur.setdefault(name, []).append((float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9)
+    out = [f"# SQ counters per kernel: {a.title}", "", "Commands:", "", "```"] + list(a.command or []) + ["```", ""]
+    if a.note:
+        out += [a.note, ""]
+    out += ["VALU fraction = SQ_INSTS_VALU / (average duration x 256 CUs x 2.4 GHz), durations from the kernel "
+            "trace. LDS active = SQ_LDS_IDX_ACTIVE / (duration x 256 CUs x 2.4 GHz); conflict share = "
+            "SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE.", "",
+            "| kernel | launches | VALU instr per launch | LDS instr per launch | avg ms | VALU fraction | "
+            "LDS active | conflict share |", "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    rows = []
+    for name, disp in per.items():
+        n = len(disp)
+        tot = {}
+        for d in disp.values():
+            for k, v in d.items():
+                tot[k] = tot.get(k, 0.0) + v
+        ds = dur.get(name)
+        avg = sum(ds) / len(ds) if ds else 0.0
+        valu = tot.get("SQ_INSTS_VALU", 0.0) / n
+        lds = tot.get("SQ_INSTS_LDS", 0.0) / n
+        act = tot.get("SQ_LDS_IDX_ACTIVE", 0.0) / n
+        conf = tot.get("SQ_LDS_BANK_CONFLICT", 0.0) / n
+        vf = valu / (avg * PEAK_WAVE_INSTR_PER_S) if avg else 0.0
+        lf = act / (avg * PEAK_WAVE_INSTR_PER_S) if avg else 0.0
+        rows.append((avg * len(ds or []), name, n, valu, lds, avg, vf, lf, conf / act if act else 0.0))
+    for _, name, n, valu, lds, avg, vf, lf, cs in sorted(rows, reverse=True)[: a.top]:
+        out.append(f"| `{name[:80]}` | {n} | {valu:.3e} | {lds:.3e} | {avg * 1e3:.3f} | {vf:.3f} | {lf:.3f} | {cs:.3f} |")
+    with open(a.out, "w") as f:
+        f.write("\n".join(out) + "\n")
+
+
 def main(argv=None) -> None:
     ap = argparse.ArgumentParser(prog="python -m paper_2509_19162_amd.profiling")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -197,8 +245,16 @@ def main(argv=None) -> None:
     c.add_argument("--command", action="append")
     c.add_argument("--top", type=int, default=12)
     c.add_argument("--out", required=True)
+    q = sub.add_parser("sq")
+    q.add_argument("--title", default="")
+    q.add_argument("--note", default="")
+    q.add_argument("--csv", required=True, help="run_counter_collection.csv of the SQ counter run")
+    q.add_argument("--trace", required=True, help="run_kernel_trace.csv of the same command")
+    q.add_argument("--command", action="append")
+    q.add_argument("--top", type=int, default=10)
+    q.add_argument("--out", required=True)
     a = ap.parse_args(argv)
-    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters, "sq": cmd_sq}[a.cmd](a)
 
 
 if __name__ == "__main__":
