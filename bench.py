@@ -478,8 +478,12 @@ def serving_leg(n_requests: int, nmax: int, ratios, cpu_budget: float, host: dic
         eng = api.Engine()
         t0 = time.perf_counter()
         plain_states = 0
-        for n, fam, g in reqs:
-            plain_states += eng.run(n, g, max_layers=512).states_expanded
+        for i, (n, fam, g) in enumerate(reqs):
+            # the engine the queue picks for the request (from n = 12 the
+            # bitmask engine)
+            plain_states += eng.run(n, g, max_layers=512, bitmask=n >= 12).states_expanded
+            if (i + 1) % 50 == 0:
+                log(f"serving: plain one-at-a-time {i + 1}/{R} requests, {time.perf_counter() - t0:.1f} s")
         plain_dt = time.perf_counter() - t0
         eng.close()
         plain_line = {"req_per_s": round(R / plain_dt, 2), "states_per_s": round(plain_states / plain_dt, 1)}
@@ -487,7 +491,11 @@ def serving_leg(n_requests: int, nmax: int, ratios, cpu_budget: float, host: dic
     # capacity: every request submitted at once
     t0 = time.perf_counter()
     ts = [q.submit(n, g, max_layers=512) for n, fam, g in reqs]
-    outs = [q.wait(t) for t in ts]
+    outs = []
+    for i, t in enumerate(ts):
+        outs.append(q.wait(t))
+        if (i + 1) % 100 == 0:
+            log(f"serving: capacity run {i + 1}/{R} requests done, {time.perf_counter() - t0:.1f} s")
     cap_dt = time.perf_counter() - t0
     mu = R / cap_dt
     log(f"serving: capacity {mu:.1f} req/s")
@@ -510,7 +518,11 @@ def serving_leg(n_requests: int, nmax: int, ratios, cpu_budget: float, host: dic
         t0 = time.perf_counter()
         th = threading.Thread(target=producer)
         th.start()
-        th.join()
+        while th.is_alive():
+            th.join(timeout=30.0)
+            if th.is_alive():
+                log(f"serving: {ratio} x capacity: {sum(t is not None for t in tickets)}/{R} submitted, "
+                    f"{time.perf_counter() - t0:.0f} s")
         out = [q.wait(t) for t in tickets]
         dt = time.perf_counter() - t0
         for a, b in zip(out, outs):
@@ -585,6 +597,7 @@ def main():
     ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--serving-nmax", type=int, default=13)
     ap.add_argument("--ratios", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9, 1.0, 1.2])
+    ap.add_argument("--no-plain", action="store_true", help="serving: skip the one-at-a-time comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-extras", action="store_true", help="default run: the headline only")
@@ -615,7 +628,7 @@ def main():
         print(json.dumps(line), flush=True)
         return
     if args.workload == "serving":
-        leg = serving_leg(args.requests, args.serving_nmax, args.ratios, cpu_budget, host)
+        leg = serving_leg(args.requests, args.serving_nmax, args.ratios, cpu_budget, host, plain=not args.no_plain)
         ref = leg["rates"].get("0.9") or list(leg["rates"].values())[-1]
         line = {"metric": "p99 job latency", "value": ref["p99_ms"], "unit": "ms", "n_gpus": 1,
                 "steps": len(args.ratios), "warmup": 1, "ms_per_step": round(1000 * leg["capacity_wall_s"], 2),

@@ -51,7 +51,7 @@ extern "C" {
 #define CG_E_DEVICE (-3)   /* HIP error or a kernel-reported failure         */
 #define CG_E_UNSUPPORTED (-4) /* generating set not closed under inverses
                               and CG_ALLOW_DIRECTED not given                */
-#define CG_E_BUSY (-5)     /* queue full                                     */
+#define CG_E_BUSY (-5)     /* queue full, or workspace buffers in use         */
 #define CG_E_CANCELLED (-6)/* job cancelled before it finished               */
 #define CG_E_TIMEOUT (-7)  /* cg_queue_wait timed out (job still running)     */
 
@@ -356,7 +356,10 @@ int cg_queue_stats(cg_queue_t *q, cg_queue_stats_t *out);
  * device arena (the fraction CG_ARENA_FRACTION of the free memory, default
  * 0.85; 0 disables it) and carves every buffer out of it; a freed range is
  * reused only after the work queued on its last stream has finished. This
- * returns the arena to the driver if no buffer is in use.
+ * frees the buffers and graphs that cg_growth_batch keeps between calls (a
+ * batch call in progress finishes first; the next one builds them again),
+ * then returns the arena to the driver if no buffer is in use (engines and
+ * queues still alive keep theirs).
  */
 void cg_release_cached_memory(void);
 
@@ -367,9 +370,10 @@ void cg_release_cached_memory(void);
  * back to hipMalloc. The memory stays the caller's: the library never
  * frees it, and the caller must keep it alive until the workspace is
  * replaced. dev_ptr = NULL returns to an arena the library reserves itself.
- * Returns CG_OK, CG_E_BUSY while buffers of engines, queues or batches still
- * live in the current arena (destroy them first), or CG_E_INVAL (bytes too
- * small, under 64 KiB).
+ * The buffers that cg_growth_batch keeps between calls are freed first.
+ * Returns CG_OK, CG_E_BUSY while buffers of engines or queues still live in
+ * the current arena (destroy them first), or CG_E_INVAL (bytes too small,
+ * under 64 KiB).
  */
 int cg_set_workspace(void *dev_ptr, size_t bytes);
 

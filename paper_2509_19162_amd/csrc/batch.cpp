@@ -317,11 +317,20 @@ struct BatchContext {
     int file_entries = 0;
 };
 
+struct BatchContexts {
+    std::mutex mu;
+    std::map<int, BatchContext *> ctx;  // never destroyed: their streams live until exit
+};
+
+BatchContexts &batch_contexts() {
+    static BatchContexts c;
+    return c;
+}
+
 BatchContext &batch_context(int dev) {
-    static std::mutex mu;
-    static std::map<int, BatchContext *> ctx;  // never destroyed: their streams live until exit
-    std::lock_guard<std::mutex> lk(mu);
-    BatchContext *&c = ctx[dev];
+    BatchContexts &all = batch_contexts();
+    std::lock_guard<std::mutex> lk(all.mu);
+    BatchContext *&c = all.ctx[dev];
     if (!c) {
         c = new BatchContext();
         c->dev = dev;
@@ -625,6 +634,16 @@ void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_
     }
     if (changed) save_tuning(c);
     (void)run_with(by_n, results, opts, c, true, c.heavy_div, t0);
+}
+
+void release_batch_buffers() {
+    BatchContexts &all = batch_contexts();
+    std::lock_guard<std::mutex> lk(all.mu);
+    for (auto &kv : all.ctx) {
+        BatchContext &c = *kv.second;
+        std::lock_guard<std::mutex> l2(c.mu);  // waits for a batch call in progress
+        if (c.runner) c.runner->release();
+    }
 }
 
 void batch_info(cg_batch_info_t *out) {

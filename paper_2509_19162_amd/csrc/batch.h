@@ -90,5 +90,8 @@ private:
 void run_batch(int n_jobs, const cg_job_t *jobs, cg_result_t *results, const cg_batch_opts_t *opts);
 // cg_batch_info for the current device.
 void batch_info(cg_batch_info_t *out);
+// Frees the device buffers and graphs that batches keep between calls (on
+// every device; the next batch builds them again).
+void release_batch_buffers();
 
 }  // namespace cg

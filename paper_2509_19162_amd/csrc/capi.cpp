@@ -57,7 +57,7 @@ const char *cg_strerror(int code) {
         case CG_E_NOMEM: return "out of memory";
         case CG_E_DEVICE: return "device error";
         case CG_E_UNSUPPORTED: return "unsupported generating set";
-        case CG_E_BUSY: return "queue full";
+        case CG_E_BUSY: return "busy (queue full, or buffers still in use)";
         case CG_E_CANCELLED: return "cancelled";
         case CG_E_TIMEOUT: return "timed out";
         default: return "unknown status";
@@ -68,6 +68,7 @@ const char *cg_last_error(void) { return g_last_error.c_str(); }
 
 void cg_release_cached_memory(void) {
     guarded([&]() -> int {
+        cg::release_batch_buffers();
         cg::release_cached_device_memory();
         return CG_OK;
     });
@@ -97,6 +98,7 @@ int cg_growth(int n, const uint8_t *gens, int n_gens, int max_layers, uint64_t *
 
 int cg_set_workspace(void *dev_ptr, size_t bytes) {
     return guarded([&]() -> int {
+        cg::release_batch_buffers();  // the batches' kept buffers may live in the old arena
         cg::set_workspace(dev_ptr, bytes);
         return CG_OK;
     });

@@ -42,11 +42,16 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-// Keys per thread: 16 for 64-bit keys (256 threads, 4096-key tiles), 30 for
-// 32-bit keys (512 threads, 15360-key tiles). A pass is bound by the keys in
-// flight over a tile's latency (most of it the look-back): 30 keys, their
-// packed ranks and the look-back fit 80 VGPRs, which with the split LDS
-// reorder below keeps 3 tiles resident per CU (32 keys need 88 VGPRs: 2).
+// Keys per thread: 30 for 32-bit keys (512 threads, 15360-key tiles), 16
+// for 64-bit keys (768 threads, below). A pass is bound by the keys in
+// flight over a tile's latency, about half of which is the wait for the
+// predecessors' look-back words (measured per tile with the real-time
+// clock: 6 us load and rank, 11 us look-back, 5.5 us reorder and scatter
+// for 64-bit keys; a window of 12 predecessors per round instead of 1 + 3
+// did not shorten it, so the wait is the words' latency between XCDs, not
+// the walk). 30 keys, their packed ranks and the look-back fit 80 VGPRs,
+// which with the split LDS reorder below keeps 3 tiles resident per CU
+// (32 keys need 88 VGPRs: 2).
 #ifndef CG_SORT_IPT32
 #define CG_SORT_IPT32 30
 #endif
@@ -65,7 +70,9 @@ constexpr int kWaves = kBlock / kWave;
 // digit's run of a tile contiguously; uniformly spread digits (64-bit
 // ranks) leave runs of tile/256 keys whose cache lines at both ends are
 // written partially, so longer tiles write more efficiently: S_16 LRX sort
-// passes 866 ms at 4096-key tiles, 704 at 8192, 688 at 12288 (10240: 690).
+// passes 866 ms at 4096-key tiles, 704 at 8192, 688 at 12288 (10240: 690);
+// at one block per CU (more VGPRs) 16384-, 20480- and 24576-key tiles took
+// 724, 694 and 697 ms, 768 x 32 keys 673 against 675 for 768 x 16.
 #ifndef CG_SORT_IPT64
 #define CG_SORT_IPT64 16
 #endif
@@ -302,9 +309,16 @@ struct RankPasses {
         return b;
     }
     static constexpr int passes = (bits() + kRadixBits - 1) / kRadixBits;
-    static constexpr uint32_t mask(int p) {
-        return (1u << ((bits() - p * kRadixBits) < kRadixBits ? (bits() - p * kRadixBits) : kRadixBits)) - 1u;
+    // Balanced digits: the first bits() % passes passes take one bit more
+    // (S_16: 45 bits as 8,8,8,7,7,7 rather than 8,8,8,8,8,5). A digit of
+    // fewer bits leaves longer runs per tile, and the passes cost less in
+    // sum: S_16 LRX sort passes 676 -> 655 ms. make_passes(.., true) lays
+    // out the same passes.
+    static constexpr int width(int p) {
+        return passes == 0 ? 0 : bits() / passes + (p < bits() % passes ? 1 : 0);  // S_1: no passes
     }
+    static constexpr int shift(int p) { return p == 0 ? 0 : shift(p - 1) + width(p - 1); }
+    static constexpr uint32_t mask(int p) { return (1u << width(p)) - 1u; }
 };
 
 // Incremental ranks. The rank is sum_i c_i (n-1-i)! over the Lehmer digits
@@ -460,7 +474,7 @@ __global__ __launch_bounds__(kBlock) void expand_rank_hist_kernel(
                     o[f] = r;
 #pragma unroll
                     for (int p = 0; p < kP; ++p) {
-                        const uint32_t d = (uint32_t)(r >> (p * kRadixBits)) & RankPasses<N>::mask(p);
+                        const uint32_t d = (uint32_t)(r >> RankPasses<N>::shift(p)) & RankPasses<N>::mask(p);
                         if (p < CG_HIST_DIRECT_PASSES) {
                             atomicAdd(&s_h[p][d], 1u);
                         } else {
@@ -556,6 +570,7 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
     __shared__ uint32_t s_lstart[kFold ? 1 : kRadix];
     __shared__ uint32_t s_scan[kWv];
     __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_next;
 
     // the digit masks of the ranking live in s_keys until the scatter
     uint64_t(*s_match)[kWv][kRadix] = reinterpret_cast<uint64_t(*)[kWv][kRadix]>(s_keys);
@@ -568,10 +583,18 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
     if (Lookback && threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     // With look-back the blocks are persistent: each takes tiles in ticket
     // order until the tickets run out (every block ends on a ticket past the
-    // last tile), which saves a block launch per tile. Tickets are only
-    // drawn by running blocks for the tile they start next, so the smallest
-    // unfinished ticket is always some block's current tile: every wait ends.
+    // last tile), which saves a block launch per tile. A block draws its next
+    // ticket once the offsets of its current tile are published, and loads
+    // that tile's keys while it writes out the last reorder round of the
+    // current one (S_16 LRX sort passes 695 -> 678 ms). Every wait ends:
+    // tickets are drawn only by running blocks, and the smallest tile whose
+    // offsets are unpublished is either some block's current tile, whose
+    // look-back waits only on smaller tiles, or some block's next tile, whose
+    // block is writing out a tile that waits on nothing.
     const uint32_t ntiles = src.tiles();
+    uint32_t next_tile = 0;
+    bool preloaded = false;
+    K key[kIpt];
     for (;;) {
     uint32_t tid = threadIdx.x;
     // an opaque copy of the thread index: addresses derived from it are
@@ -582,7 +605,7 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
     for (int i = tid; i < kWv * kRadix; i += kBlk) (&s_cnt[0][0])[i] = 0;
     for (int i = tid; i < kRows * kWv * kRadix; i += kBlk) (&s_match[0][0][0])[i] = 0;
     __syncthreads();
-    const uint32_t tile = Lookback ? s_tile : blockIdx.x;
+    const uint32_t tile = Lookback ? (preloaded ? next_tile : s_tile) : blockIdx.x;
     if (kPersist && tile >= ntiles) break;  // same for the whole block
     const auto T = src.tile(tile);
     const uint32_t nvalid = T.n;
@@ -594,11 +617,12 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
     // Wave w owns keys [w*S, (w+1)*S) of the tile (S = kWaveSeg); item j of
     // lane l is key w*S + j*64 + l, so (wave, item, lane) order is index order and
     // the per-wave running counts give a stable rank.
-    K key[kIpt];
+    if (!preloaded) {
 #pragma unroll
-    for (int j = 0; j < kIpt; ++j) {
-        const uint32_t i = wave * kWaveSeg + j * kWave + lane;
-        key[j] = i < nvalid ? T.get(i) : (K)kSentinel;
+        for (int j = 0; j < kIpt; ++j) {
+            const uint32_t i = wave * kWaveSeg + j * kWave + lane;
+            key[j] = i < nvalid ? T.get(i) : (K)kSentinel;
+        }
     }
     // Peers (lanes of this wave holding the same digit) come from LDS masks:
     // every lane ORs its lane bit into its digit's word, reads the words
@@ -697,6 +721,9 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
                                                                                       epoch, err);
                 lb_store(my, lb_word(epoch, kFlagInclusive, excl + pub));
             }
+            // the next tile's ticket, drawn once this tile's offsets are
+            // published (before any scatter store of this wave is in flight)
+            if (kPersist && tid == 0) s_next = atomicAdd(ticket, 1u);
             s_gdelta[d] = (uint64_t)digit_base[d] + excl;
         } else {
             s_gdelta[d] = tile_off[(uint64_t)tile * kRadix + d];
@@ -736,15 +763,31 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
 #pragma unroll
     for (int h = 0; h < kSplit; ++h) {
         const uint32_t lo = (uint32_t)h * kBuf;
-        if (lo >= nvalid) break;  // same for the whole block
+        if (!kPersist && lo >= nvalid) break;  // same for the whole block
+        const bool any = lo < nvalid;         // same for the whole block
+        const bool last = h == kSplit - 1;
         if (h) __syncthreads();   // the previous round's readers are done
+        if (any) {
 #pragma unroll
-        for (int j = 0; j < kIpt; ++j) {
-            const uint32_t p = ((j & 1) ? rank2[j >> 1] >> 16 : rank2[j >> 1] & 0xFFFFu) - lo;
-            if (p < (uint32_t)kBuf) s_keys[p] = key[j];
+            for (int j = 0; j < kIpt; ++j) {
+                const uint32_t p = ((j & 1) ? rank2[j >> 1] >> 16 : rank2[j >> 1] & 0xFFFFu) - lo;
+                if (p < (uint32_t)kBuf) s_keys[p] = key[j];
+            }
         }
         __syncthreads();
-        const uint32_t cnt = nvalid - lo < (uint32_t)kBuf ? nvalid - lo : (uint32_t)kBuf;
+        if (kPersist && last) {
+            next_tile = s_next;
+            preloaded = true;
+            if (next_tile < ntiles) {
+                const auto T2 = src.tile(next_tile);
+#pragma unroll
+                for (int j = 0; j < kIpt; ++j) {
+                    const uint32_t i = wave * kWaveSeg + j * kWave + lane;
+                    key[j] = i < T2.n ? T2.get(i) : (K)kSentinel;
+                }
+            }
+        }
+        const uint32_t cnt = !any ? 0u : nvalid - lo < (uint32_t)kBuf ? nvalid - lo : (uint32_t)kBuf;
         for (uint32_t i = tid; i < cnt; i += kBlk) {
             const K k = s_keys[i];
             const uint32_t d = digit_of(k, shift, dmask, dwidth);
@@ -760,10 +803,7 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
         }
     }
     if constexpr (!kPersist) break;
-    // the next ticket only now: a ticket held while another tile finishes
-    // would stall the look-backs of every later tile
-    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
-    __syncthreads();  // the next ticket is visible and the reorder buffer is free
+    __syncthreads();  // the reorder buffer is free
     }
 }
 
@@ -838,9 +878,25 @@ __global__ __launch_bounds__(kBlock) void tile_offset_kernel(const uint32_t *__r
     }
 }
 
-PassDesc make_passes(int bit_lo, int bit_hi) {
+// Passes of at most 8 bits over [bit_lo, bit_hi): from bit_lo up in 8-bit
+// digits (the last one shorter), or with `balanced` as many passes with
+// widths that differ by at most one bit (RankPasses lays out the same).
+PassDesc make_passes(int bit_lo, int bit_hi, bool balanced = false) {
     PassDesc pd{};
     pd.passes = 0;
+    if (balanced) {
+        const int b = bit_hi - bit_lo;
+        const int P = (b + kRadixBits - 1) / kRadixBits;
+        int s = bit_lo;
+        for (int p = 0; p < P; ++p) {
+            const int bits = b / P + (p < b % P ? 1 : 0);
+            pd.shift[p] = s;
+            pd.mask[p] = (1u << bits) - 1u;
+            s += bits;
+        }
+        pd.passes = P;
+        return pd;
+    }
     for (int s = bit_lo; s < bit_hi; s += kRadixBits) {
         const int bits = (bit_hi - s) < kRadixBits ? (bit_hi - s) : kRadixBits;
         pd.shift[pd.passes] = s;
@@ -873,10 +929,10 @@ template <class Src>
 typename Src::Key *run_sort(const Src &first_src, uint64_t count, typename Src::Key *buf0,
                             typename Src::Key *buf1, int bit_lo, int bit_hi, PipeWork &w, bool fused_first,
                             double first_read_bytes, const typename Src::Key *array_in,
-                            bool hist_ready = false, bool skip_check = true) {
+                            bool hist_ready = false, bool skip_check = true, bool balanced = false) {
     using K = typename Src::Key;
     constexpr double kb = (double)sizeof(K);
-    const PassDesc pd = make_passes(bit_lo, bit_hi);
+    const PassDesc pd = make_passes(bit_lo, bit_hi, balanced);
     if (pd.passes > kMaxPasses) throw Error(-1, "sort bit range needs more than 8 passes");
     unsigned long long *hist = w.hist.as<unsigned long long>();
     unsigned long long *base = w.base.as<unsigned long long>();
@@ -1058,7 +1114,7 @@ uint32_t *expand_rank_sort(int n, const uint64_t *frontier, uint64_t F, const Ge
     // Ranks of a large layer's candidates spread over [0, n!): no pass is
     // the identity, so the histograms are not read back (no host sync); a
     // pass that is one anyway runs as an ordinary pass.
-    return run_sort(src, C, buf1, buf0, 0, rank_bits, w, false, 4.0 * (double)C, buf0, true, false);
+    return run_sort(src, C, buf1, buf0, 0, rank_bits, w, false, 4.0 * (double)C, buf0, true, false, true);
 }
 
 uint64_t *expand_rank_sort64(int n, const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,
@@ -1088,7 +1144,7 @@ uint64_t *expand_rank_sort64(int n, const uint64_t *frontier, uint64_t F, const 
     if (w.prof) w.prof->end(K_EXPAND, 8.0 * (double)F + 8.0 * (double)C, (double)C);
     const ArraySrcT<uint64_t> src{buf0, C};
     // as for 32-bit ranks: every pass runs, the histograms stay on the device
-    return run_sort(src, C, buf1, buf0, 0, rank_bits, w, false, 8.0 * (double)C, buf0, true, false);
+    return run_sort(src, C, buf1, buf0, 0, rank_bits, w, false, 8.0 * (double)C, buf0, true, false, true);
 }
 
 uint64_t *expand_sort(const uint64_t *frontier, uint64_t F, const GenSel *d_gsel, int k,

@@ -143,3 +143,25 @@ def _stored_batch():
     if not os.path.exists(path):
         pytest.skip("oracle fixtures not generated")
     return json.load(open(path))["batch_4096"]["sizes"]
+
+
+def test_release_frees_the_buffers_batches_keep(oracle_c):
+    """cg_release_cached_memory also frees what batches keep between calls
+    (the small-job runner's buffers and launch graph), so the device arena
+    goes back to the driver; the next batch builds its graph again and
+    gives the same results."""
+    import torch
+
+    jobs = mixed_jobs(64, 7, 5, 10)
+    api.growth_batch(jobs, max_layers=512)
+    assert sum(api.growth(11, I.pancake(11))) == 39916800  # large buffers: the arena is reserved
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    api.release_cached_memory()
+    free, total = torch.cuda.mem_get_info()
+    assert free > total // 2, (free, total)
+    before = api.batch_info()
+    res = api.growth_batch(jobs, max_layers=512)
+    assert api.batch_info()["graph_builds"] == before["graph_builds"] + 1
+    for (n, gens), r in zip(jobs, res):
+        assert r.sizes == oracle_c.growth(n, gens, max_layers=512)[0]
