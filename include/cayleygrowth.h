@@ -43,10 +43,11 @@ extern "C" {
 #define CG_TRUNCATED 1     /* a stop rule ended the search (max_layers,
                               max_frontier); the last layer is non-empty     */
 #define CG_PENDING 2       /* queue: the job has not finished yet            */
-#define CG_E_INVAL (-1)    /* bad argument: n outside 1..16, n_gens < 1, a
-                              generator row that is not a permutation of
-                              0..n-1, max_layers < 1, NULL pointer, start
-                              entry > 15                                      */
+#define CG_E_INVAL (-1)    /* bad argument: n outside 1..16 (1..64 for
+                              binary states), n_gens < 1, a generator row
+                              that is not a permutation of 0..n-1,
+                              max_layers < 1, NULL pointer, start entry > 15
+                              (> 1 for binary states)                        */
 #define CG_E_NOMEM (-2)    /* device or host memory exhausted                */
 #define CG_E_DEVICE (-3)   /* HIP error or a kernel-reported failure         */
 #define CG_E_UNSUPPORTED (-4) /* generating set not closed under inverses
@@ -85,10 +86,21 @@ extern "C" {
                                     in LDS or a device slot; on a reusable
                                     engine the launch is a hipGraph that is
                                     replayed while the job's shape repeats */
+#define CG_BINARY_STATE 0x80u    /* binary states: with CG_START_STATE and a
+                                    0/1 start vector, pack one bit per entry
+                                    instead of four (the Schreier coset
+                                    graphs of the paper's section "Growth of
+                                    Reversals and Transposons on binary
+                                    cosets"). Implied for n > 16, up to
+                                    n = 64. Sort path only (no CG_BITMASK,
+                                    CG_SMALL_JOB, batches or queue); a
+                                    layer's candidates must fit in device
+                                    memory at once (no key-range chunks).   */
 
 /*
  * A growth job.
- *   n            entries per state, 1..16 (each entry is packed in 4 bits)
+ *   n            entries per state, 1..16 (each entry is packed in 4 bits);
+ *                17..64 for binary states (CG_BINARY_STATE: 1 bit each)
  *   gens         n_gens rows of n bytes, row-major; row g holds the one-line
  *                images g[0..n-1]. Duplicate rows and the identity are
  *                allowed and ignored (they do not change any layer).
@@ -98,8 +110,8 @@ extern "C" {
  *   max_frontier 0 = none; otherwise the first layer whose size is strictly
  *                greater than this is recorded and not expanded
  *   flags        CG_* job flags
- *   start        n bytes with entries 0..15 when CG_START_STATE is set,
- *                else ignored (NULL allowed)
+ *   start        n bytes with entries 0..15 (0..1 for binary states) when
+ *                CG_START_STATE is set, else ignored (NULL allowed)
  *   layers_out   optional host buffer (NULL = none): receives every
  *                recorded layer's states, layer after layer, each layer in
  *                increasing lexicographic order, n bytes per state

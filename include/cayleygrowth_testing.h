@@ -121,6 +121,16 @@ int cg_test_copy(const void *d_src, void *d_dst, uint64_t bytes, int repeats, vo
 int cg_test_host_expand(int n, const uint8_t *h_gens, int k, const uint64_t *h_frontier,
                         uint64_t F, uint64_t *h_out);
 
+/*
+ * The expand of binary states (one bit per entry, entry i at bit n-1-i,
+ * n <= 64) applied on the host with the byte tables the GPU kernel uses:
+ * h_out[g*F + f] = key(s_f . g), the OR of one table entry per key byte.
+ * Checks the tables without a GPU. h_gens: k rows of n bytes, each a
+ * permutation of 0..n-1. Returns CG_OK or CG_E_INVAL.
+ */
+int cg_test_host_expand_bits(int n, const uint8_t *h_gens, int k, const uint64_t *h_frontier,
+                             uint64_t F, uint64_t *h_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,6 +31,7 @@ CG_PROFILE = 0x8
 CG_PACKED_SORT = 0x10
 CG_BITMASK = 0x20
 CG_SMALL_JOB = 0x40
+CG_BINARY_STATE = 0x80
 
 CG_KSTAT_MAX = 8
 
@@ -192,6 +193,7 @@ SIGNATURES = [
     ("cg_test_unrank64", ctypes.c_int,
      [ctypes.c_int, u64p, ctypes.c_uint64, u64p, ctypes.c_int, ctypes.c_void_p]),
     ("cg_test_host_expand", ctypes.c_int, [ctypes.c_int, u8p, ctypes.c_int, u64p, ctypes.c_uint64, u64p]),
+    ("cg_test_host_expand_bits", ctypes.c_int, [ctypes.c_int, u8p, ctypes.c_int, u64p, ctypes.c_uint64, u64p]),
     ("cg_test_copy", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]),
     ("cg_test_layer_step", ctypes.c_int,

@@ -137,10 +137,11 @@ def growth_ex(n: int, gens: Sequence[Sequence[int]], max_layers: int = 256,
               max_frontier: Optional[int] = None, start: Optional[Sequence[int]] = None,
               keep_all_layers: bool = False, allow_directed: bool = False, profile: bool = False,
               export_layers: int = 0, stream=None, packed_sort: bool = False,
-              bitmask: bool = False, small_job: bool = False) -> GrowthResult:
+              bitmask: bool = False, small_job: bool = False, binary_state: bool = False) -> GrowthResult:
     """The full job interface (``cg_growth_ex``). ``bitmask`` selects the
     rank-space bitmap engine (n <= 14, sizes only); ``small_job`` runs the
-    job inside one workgroup (n <= 10, sizes only).
+    job inside one workgroup (n <= 10, sizes only); ``binary_state`` packs a
+    0/1 ``start`` vector one bit per entry (implied for n > 16, up to 64).
 
     ``export_layers``: capacity (in states) of the layer-content export; the
     result's ``layers`` then lists each layer's states in increasing
@@ -159,6 +160,8 @@ def growth_ex(n: int, gens: Sequence[Sequence[int]], max_layers: int = 256,
         flags |= N.CG_BITMASK
     if small_job:
         flags |= N.CG_SMALL_JOB
+    if binary_state:
+        flags |= N.CG_BINARY_STATE
     h = _JobHolder(n, gens, max_layers, max_frontier, flags, start, export_layers)
     _check(N.lib().cg_growth_ex(ctypes.byref(h.job), ctypes.byref(h.res), _stream_handle(stream)))
     return h.result()
@@ -176,11 +179,11 @@ class Engine:
     def run(self, n: int, gens, max_layers: int = 256, max_frontier: Optional[int] = None,
             start=None, keep_all_layers: bool = False, allow_directed: bool = False,
             profile: bool = False, export_layers: int = 0, packed_sort: bool = False,
-            bitmask: bool = False, small_job: bool = False) -> GrowthResult:
+            bitmask: bool = False, small_job: bool = False, binary_state: bool = False) -> GrowthResult:
         flags = (N.CG_KEEP_ALL_LAYERS if keep_all_layers else 0) | \
                 (N.CG_ALLOW_DIRECTED if allow_directed else 0) | (N.CG_PROFILE if profile else 0) | \
                 (N.CG_PACKED_SORT if packed_sort else 0) | (N.CG_BITMASK if bitmask else 0) | \
-                (N.CG_SMALL_JOB if small_job else 0)
+                (N.CG_SMALL_JOB if small_job else 0) | (N.CG_BINARY_STATE if binary_state else 0)
         h = _JobHolder(n, gens, max_layers, max_frontier, flags, start, export_layers)
         _check(N.lib().cg_engine_run(self._e, ctypes.byref(h.job), ctypes.byref(h.res)))
         return h.result()

@@ -552,4 +552,31 @@ int cg_test_host_expand(int n, const uint8_t *h_gens, int k, const uint64_t *h_f
     });
 }
 
+int cg_test_host_expand_bits(int n, const uint8_t *h_gens, int k, const uint64_t *h_frontier, uint64_t F,
+                             uint64_t *h_out) {
+    return guarded([&]() -> int {
+        if (n < 1 || n > 64 || k < 1 || !h_gens) throw cg::Error(CG_E_INVAL, "bad generator arguments");
+        if (F && (!h_frontier || !h_out)) throw cg::Error(CG_E_INVAL, "NULL pointer");
+        for (int g = 0; g < k; ++g) {
+            bool seen[64] = {false};
+            for (int i = 0; i < n; ++i) {
+                const uint8_t v = h_gens[(size_t)g * n + i];
+                if (v >= n || seen[v]) throw cg::Error(CG_E_INVAL, "generator row is not a permutation");
+                seen[v] = true;
+            }
+        }
+        const std::vector<uint64_t> t = cg::make_bit_tables(n, h_gens, k);
+        const int nb = (n + 7) / 8;
+        for (int g = 0; g < k; ++g) {
+            const uint64_t *tg = t.data() + (size_t)g * nb * 256;
+            for (uint64_t f = 0; f < F; ++f) {
+                uint64_t x = 0;
+                for (int b = 0; b < nb; ++b) x |= tg[b * 256 + ((h_frontier[f] >> (8 * b)) & 255u)];
+                h_out[(uint64_t)g * F + f] = x;
+            }
+        }
+        return CG_OK;
+    });
+}
+
 }  // extern "C"

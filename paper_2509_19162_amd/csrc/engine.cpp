@@ -33,7 +33,14 @@ double now_seconds() {
 
 JobSpec canonicalize(const cg_job_t &job, bool batch) {
     JobSpec s;
-    if (job.n < 1 || job.n > 16) throw Error(CG_E_INVAL, "n must be in 1..16");
+    if (job.n < 1 || job.n > 64) throw Error(CG_E_INVAL, "n must be in 1..64 (above 16 with a 0/1 start vector)");
+    // one bit per entry: asked for, or needed (more than 16 entries)
+    s.binary = job.n > 16 || (job.flags & CG_BINARY_STATE);
+    if (s.binary && !(job.flags & CG_START_STATE))
+        throw Error(CG_E_INVAL, "binary states (n > 16 or CG_BINARY_STATE) need CG_START_STATE and a 0/1 start vector");
+    if (s.binary && (job.flags & (CG_BITMASK | CG_SMALL_JOB)))
+        throw Error(CG_E_INVAL, "binary states run on the sort path only");
+    if (s.binary && batch) throw Error(CG_E_UNSUPPORTED, "batches and the serving queue use 4-bit states (n <= 16)");
     if (!job.gens || job.n_gens < 1) throw Error(CG_E_INVAL, "need at least one generator row");
     if (job.max_layers < 1) throw Error(CG_E_INVAL, "max_layers must be >= 1");
     const int n = job.n;
@@ -49,7 +56,7 @@ JobSpec canonicalize(const cg_job_t &job, bool batch) {
     std::vector<std::vector<uint8_t>> rows;
     for (int g = 0; g < job.n_gens; ++g) {
         const uint8_t *r = job.gens + (size_t)g * n;
-        bool seen[16] = {false};
+        bool seen[64] = {false};
         bool ident = true;
         for (int i = 0; i < n; ++i) {
             if (r[i] >= n || seen[r[i]]) {
@@ -85,23 +92,25 @@ JobSpec canonicalize(const cg_job_t &job, bool batch) {
         if (!job.start) throw Error(CG_E_INVAL, "CG_START_STATE without a start vector");
         for (int i = 0; i < n; ++i) {
             if (job.start[i] > 15) throw Error(CG_E_INVAL, "start entries must be 0..15");
+            if (s.binary && job.start[i] > 1) throw Error(CG_E_INVAL, "binary states need a 0/1 start vector");
             s.start[i] = job.start[i];
         }
     } else {
         for (int i = 0; i < n; ++i) s.start[i] = (uint8_t)i;
     }
-    // orbit size bound: multinomial n! / prod(mult!)
+    // orbit size bound: multinomial n! / prod(mult!) (at most C(64, 32) <
+    // 2^61 for binary states, 16! for 4-bit ones)
     int mult[16] = {0};
     for (int i = 0; i < n; ++i) mult[s.start[i]]++;
-    uint64_t b = 1;
+    unsigned __int128 b = 1;
     int placed = 0;
     for (int v = 0; v < 16; ++v) {
         for (int j = 1; j <= mult[v]; ++j) {
             ++placed;
-            b = b * (uint64_t)placed / (uint64_t)j;  // exact: running binomial products
+            b = b * (unsigned)placed / (unsigned)j;  // exact: running binomial products
         }
     }
-    s.orbit_bound = b;
+    s.orbit_bound = (uint64_t)b;
     return s;
 }
 
@@ -185,7 +194,10 @@ void Engine::export_layer(const JobSpec &spec, const uint64_t *d_keys, uint64_t 
     }
     const uint64_t take = std::min(count, spec.layers_out_cap - written);
     stage_.ensure(take * (uint64_t)spec.n + 64, 1.25);
-    launch_unpack(spec.n, d_keys, take, stage_.as<uint8_t>(), stream_);
+    if (spec.binary)
+        launch_unpack_bits(spec.n, d_keys, take, stage_.as<uint8_t>(), stream_);
+    else
+        launch_unpack(spec.n, d_keys, take, stage_.as<uint8_t>(), stream_);
     CG_HIP(hipMemcpyAsync(spec.layers_out + written * spec.n, stage_.p, take * spec.n,
                           hipMemcpyDeviceToHost, stream_));
     CG_HIP(hipStreamSynchronize(stream_));
@@ -363,14 +375,22 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
     CG_HIP(hipEventRecord(ev0, stream_));
 
     uint64_t written = 0;
-    const uint64_t key0 = pack_host(n, spec.start);
+    const bool binary = spec.binary;
+    const uint64_t key0 = binary ? pack_bits_host(n, spec.start) : pack_host(n, spec.start);
+    if (binary) {
+        // per generator, the byte tables of its bit permutation
+        const std::vector<uint64_t> t = make_bit_tables(n, spec.gens.data(), k);
+        gsel_.ensure(std::max<size_t>(t.size(), 1) * sizeof(uint64_t));
+        if (!t.empty())
+            CG_HIP(hipMemcpyAsync(gsel_.p, t.data(), t.size() * sizeof(uint64_t), hipMemcpyHostToDevice, stream_));
+    }
 
     // generator selectors, followed by each generator's first position
     // from which it fixes every position
-    std::vector<GenSel> hsel(k > 0 ? k : 1);
+    std::vector<GenSel> hsel(k > 0 && !binary ? k : 1);
     std::vector<uint8_t> hfix(hsel.size(), 0);
     int moved = 0;  // Lehmer digits an incremental rank computes per state and all generators
-    for (int g = 0; g < k; ++g) {
+    for (int g = 0; g < k && !binary; ++g) {
         const uint8_t *row = spec.gens.data() + (size_t)g * n;
         hsel[g] = make_gensel(n, row);
         for (int p = 0; p < n; ++p)
@@ -379,22 +399,24 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
     }
     // then, at the next 4-byte boundary, each generator's n source shifts:
     // entry i of candidate s.g is the nibble of s at bit 4(n-1-g[i])
-    std::vector<uint32_t> hsh(hsel.size() * (size_t)n, 0);
-    for (int g = 0; g < k; ++g)
+    std::vector<uint32_t> hsh(binary ? 0 : hsel.size() * (size_t)n, 0);
+    for (int g = 0; g < k && !binary; ++g)
         for (int i = 0; i < n; ++i) hsh[(size_t)g * n + i] = 4u * (uint32_t)(n - 1 - spec.gens[(size_t)g * n + i]);
     const size_t sel_bytes = sizeof(GenSel) * hsel.size();
     const size_t sh_off = sel_bytes + ((hfix.size() + 3) & ~(size_t)3);
-    gsel_.ensure(sh_off + hsh.size() * sizeof(uint32_t));
-    CG_HIP(hipMemcpyAsync(gsel_.p, hsel.data(), sel_bytes, hipMemcpyHostToDevice, stream_));
-    CG_HIP(hipMemcpyAsync(gsel_.as<uint8_t>() + sel_bytes, hfix.data(), hfix.size(), hipMemcpyHostToDevice,
-                          stream_));
-    CG_HIP(hipMemcpyAsync(gsel_.as<uint8_t>() + sh_off, hsh.data(), hsh.size() * sizeof(uint32_t),
-                          hipMemcpyHostToDevice, stream_));
+    if (!binary) {
+        gsel_.ensure(sh_off + hsh.size() * sizeof(uint32_t));
+        CG_HIP(hipMemcpyAsync(gsel_.p, hsel.data(), sel_bytes, hipMemcpyHostToDevice, stream_));
+        CG_HIP(hipMemcpyAsync(gsel_.as<uint8_t>() + sel_bytes, hfix.data(), hfix.size(), hipMemcpyHostToDevice,
+                              stream_));
+        CG_HIP(hipMemcpyAsync(gsel_.as<uint8_t>() + sh_off, hsh.data(), hsh.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, stream_));
+    }
     // incremental ranks when the digits they compute, plus the parent's
     // suffix sums (about two full ranks per state), stay under 90% of k
     // full ranks
     const uint8_t *d_gfix =
-        (n >= 6 && k > 0 && 10 * (moved + 2 * (n - 2)) <= 9 * k * (n - 2) && !std::getenv("CG_RANK_FULL"))
+        (!binary && n >= 6 && k > 0 && 10 * (moved + 2 * (n - 2)) <= 9 * k * (n - 2) && !std::getenv("CG_RANK_FULL"))
             ? gsel_.as<uint8_t>() + sel_bytes
             : nullptr;
 
@@ -427,10 +449,12 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
     }
     export_layer(spec, keep_all ? arena_.as<uint64_t>() : lay_[1].as<uint64_t>(), 1, written);
 
-    const int bit_lo = 4, bit_hi = 4 * n;
+    // binary keys use bits [0, n); 4-bit keys [4, 4n) (the last entry of a
+    // state follows from the others)
+    const int bit_lo = binary ? 0 : 4, bit_hi = binary ? n : 4 * n;
     // Candidates sort as 32-bit lexicographic ranks when the states are
     // permutations of 0..n-1 with n <= 12 (12! < 2^32); layers stay packed.
-    bool perm_start = n <= kRankMaxN;
+    bool perm_start = !binary && n <= kRankMaxN;
     {
         bool seen[16] = {false};
         for (int i = 0; i < n && perm_start; ++i) {
@@ -442,7 +466,7 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
     // n = 13..16 with a permutation start: candidates sort as 64-bit ranks
     // (45 bits at n = 16: 6 passes of 8 bits instead of 8 over the 60 bits
     // of a packed key); reference layers are ranked as the dedup reads them
-    bool perm_any = n > kRankMaxN;
+    bool perm_any = !binary && n > kRankMaxN;
     {
         bool seen[16] = {false};
         for (int i = 0; i < n && perm_any; ++i) {
@@ -505,6 +529,8 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             }
         }
         const bool chunked = cap < C;
+        if (chunked && binary)
+            throw Error(CG_E_NOMEM, "binary states: a layer's candidates do not fit in device memory (no chunking)");
 
         const uint64_t *Ld, *Lp;
         uint64_t *out;
@@ -594,8 +620,14 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             launch_dedup_gather_ranked64(n, scratch, out, keep_all ? out_cap : N, w_, rank_out);
             rk_next = rank_out != nullptr;
         } else {
-            const uint64_t *sorted = expand_sort(Ld, F, gsel_.as<GenSel>(), k, cand0_.as<uint64_t>(),
-                                                 cand1_.as<uint64_t>(), bit_lo, bit_hi, w_);
+            const uint64_t *sorted;
+            if (binary) {
+                launch_expand_bits(Ld, F, gsel_.as<uint64_t>(), n, k, cand0_.as<uint64_t>(), w_);
+                sorted = radix_sort(cand0_.as<uint64_t>(), cand1_.as<uint64_t>(), C, bit_lo, bit_hi, w_);
+            } else {
+                sorted = expand_sort(Ld, F, gsel_.as<GenSel>(), k, cand0_.as<uint64_t>(), cand1_.as<uint64_t>(),
+                                     bit_lo, bit_hi, w_);
+            }
             uint64_t *scratch = sorted == cand0_.as<uint64_t>() ? cand1_.as<uint64_t>() : cand0_.as<uint64_t>();
             launch_dedup_count(sorted, C, Ra, na, Rb, nb, scratch, w_.counter(), w_);
             N = read_counter();

@@ -14,7 +14,8 @@ struct JobSpec {
     int k = 0;                  // distinct non-identity generators
     std::vector<uint8_t> gens;  // k rows of n bytes
     bool inverse_closed = true;
-    uint8_t start[16] = {0};
+    bool binary = false;        // one bit per entry (0/1 start vector, n <= 64)
+    uint8_t start[64] = {0};
     int max_layers = 1;
     uint64_t max_frontier = 0;
     uint32_t flags = 0;

@@ -172,6 +172,18 @@ void launch_pack(int n, const uint8_t *d_rows, uint64_t count, uint64_t *d_keys,
 void launch_unpack(int n, const uint64_t *d_keys, uint64_t count,
                    uint8_t *d_rows, hipStream_t s);
 
+// ---- bits.hip (binary states: one bit per entry, n <= 64) ------------------
+// Entry i of a 0/1 vector is bit n-1-i of its key.
+uint64_t pack_bits_host(int n, const uint8_t *s);
+// Per generator, ceil(n/8) tables of 256 words: the candidate bits that the
+// set bits of one key byte move to (k * ceil(n/8) * 256 words).
+std::vector<uint64_t> make_bit_tables(int n, const uint8_t *gens, int k);
+// out[g*F + f] = frontier[f] . g for the k generators whose tables are at
+// d_tables.
+void launch_expand_bits(const uint64_t *frontier, uint64_t F, const uint64_t *d_tables, int n, int k,
+                        uint64_t *out, PipeWork &w);
+void launch_unpack_bits(int n, const uint64_t *d_keys, uint64_t count, uint8_t *d_rows, hipStream_t s);
+
 // ---- radix_sort.hip ----------------------------------------------------------
 int sort_passes(int bit_lo, int bit_hi);
 // Sorts keys[0..count) on bits [bit_lo, bit_hi); returns the buffer that

@@ -107,3 +107,33 @@ def test_noalloc_batch_rejects_sizes_beyond_its_limits():
     res = api.growth_batch_noalloc([(6, I.lx(6))])
     assert res[0].status == N.CG_E_UNSUPPORTED
     assert lib.cg_growth_batch_noalloc(-1, None, None, None) == N.CG_E_INVAL
+
+
+def test_binary_state_jobs_are_validated():
+    """Binary states (one bit per entry) need a 0/1 start vector; n runs to
+    64; they take the sort path only. All rejected before any device call."""
+    lib = N.lib()
+    sizes = np.zeros(8, dtype=np.uint64)
+
+    def run(n, start, flags, gens=None):
+        g = np.ascontiguousarray(np.asarray(gens if gens is not None else [I.coxeter(n)[0]], dtype=np.uint8))
+        st = None if start is None else np.ascontiguousarray(np.asarray(start, dtype=np.uint8))
+        job = N.CgJob(n, g.ctypes.data_as(N.u8p), g.shape[0], 8, 0, flags,
+                      None if st is None else st.ctypes.data_as(N.u8p), None, 0)
+        res = N.CgResult()
+        res.layer_sizes = sizes.ctypes.data_as(N.u64p)
+        return lib.cg_growth_ex(ctypes.byref(job), ctypes.byref(res), None), lib.cg_last_error().decode()
+
+    half = lambda n: [0] * (n // 2) + [1] * (n - n // 2)  # noqa: E731
+    rc, msg = run(65, half(65), N.CG_START_STATE, gens=[list(range(65))])
+    assert rc == N.CG_E_INVAL and "1..64" in msg
+    rc, msg = run(20, None, 0)
+    assert rc == N.CG_E_INVAL and "start" in msg
+    rc, msg = run(20, [2] + half(19), N.CG_START_STATE)
+    assert rc == N.CG_E_INVAL and "0/1" in msg
+    rc, msg = run(8, None, N.CG_BINARY_STATE)
+    assert rc == N.CG_E_INVAL and "start" in msg
+    rc, msg = run(20, half(20), N.CG_START_STATE | N.CG_BITMASK)
+    assert rc == N.CG_E_INVAL and "sort path" in msg
+    rc, msg = run(20, half(20), N.CG_START_STATE | N.CG_SMALL_JOB)
+    assert rc == N.CG_E_INVAL and "sort path" in msg

@@ -136,3 +136,43 @@ def test_rank64_rejects_bad_input():
     r[0] = math.factorial(13)
     assert N.lib().cg_test_unrank64(13, r.ctypes.data_as(N.u64p), 1, k.ctypes.data_as(N.u64p), 0,
                                     None) == N.CG_E_INVAL
+
+
+def pack_bits(n, rows):
+    rows = np.asarray(rows, dtype=np.uint64).reshape(-1, n)
+    shifts = np.array([n - 1 - i for i in range(n)], dtype=np.uint64)
+    return np.bitwise_or.reduce(rows << shifts, axis=1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 8, 9, 17, 24, 31, 32, 33, 40, 57, 63, 64])
+def test_host_expand_bits_matches_gather(n):
+    """Binary states (one bit per entry): the byte tables of the bit
+    permutation, applied on the host, give key(s . g) with t[i] = s[g[i]]
+    for random 0/1 vectors and random permutations."""
+    rng = np.random.default_rng(500 + n)
+    gens = [list(map(int, rng.permutation(n))) for _ in range(6)]
+    if n > 1:
+        gens.append([n - 1 - i for i in range(n)])  # the full reversal
+        gens.append([(i + 1) % n for i in range(n)])  # a rotation
+    rows = rng.integers(0, 2, size=(300, n)).astype(np.uint8)
+    rows[0] = 0
+    rows[1] = 1
+    keys = np.ascontiguousarray(pack_bits(n, rows))
+    g = np.ascontiguousarray(np.asarray(gens, dtype=np.uint8))
+    out = np.zeros(len(gens) * len(keys), dtype=np.uint64)
+    rc = N.lib().cg_test_host_expand_bits(n, g.ctypes.data_as(N.u8p), len(gens), keys.ctypes.data_as(N.u64p),
+                                          len(keys), out.ctypes.data_as(N.u64p))
+    assert rc == 0
+    expected = np.concatenate([pack_bits(n, rows[:, gg]) for gg in gens])
+    assert np.array_equal(out, expected)
+
+
+def test_host_expand_bits_rejects_bad_rows():
+    k = np.zeros(1, dtype=np.uint64)
+    o = np.zeros(1, dtype=np.uint64)
+    bad = np.zeros((1, 20), dtype=np.uint8)  # not a permutation
+    assert N.lib().cg_test_host_expand_bits(20, bad.ctypes.data_as(N.u8p), 1, k.ctypes.data_as(N.u64p), 1,
+                                            o.ctypes.data_as(N.u64p)) == N.CG_E_INVAL
+    g = np.arange(65, dtype=np.uint8).reshape(1, 65)
+    assert N.lib().cg_test_host_expand_bits(65, g.ctypes.data_as(N.u8p), 1, k.ctypes.data_as(N.u64p), 1,
+                                            o.ctypes.data_as(N.u64p)) == N.CG_E_INVAL
