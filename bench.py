@@ -51,6 +51,10 @@ WORKLOADS = {
                       desc="S_13, 12 prefix reversals (pancake), full BFS, bitmask engine"),
     "coxeter14": dict(n=14, family="coxeter", keep_all=False, max_frontier=None, bitmask=True,
                       desc="S_14, 13 adjacent transpositions, full BFS, bitmask engine"),
+    # a Schreier coset graph with one bit per entry
+    "coset38": dict(n=38, family="lrx", keep_all=False, max_frontier=None, binary_start=True,
+                    desc="Schreier coset graph of the binary central state (19 zeros then 19 ones) under LRX, "
+                         "n = 38: full BFS over all C(38,19) = 3.5e10 states, one bit per entry"),
 }
 
 # requests of the serving point in the default run (the full sweep takes 500)
@@ -156,17 +160,25 @@ def copy_ceiling(nbytes: int = 4 << 30, repeats: int = 5) -> dict:
 def cpu_baseline(workload: dict, budget_s: float, host: dict):
     """The CPU oracle (single thread) on the first layers of the same
     workload: the largest layer prefix whose expansion fits the budget."""
-    from oracle import native
+    from oracle import bfs_set, native
     from paper_2509_19162_amd import inputs as I
 
     native.build(force=False)
     n = workload["n"]
     gens = I.family(workload["family"], n)
+    start = I.binary_central_state(n) if workload.get("binary_start") else None
+    # the C oracle packs 4 bits per entry (n <= 16); longer binary states
+    # take the Python set BFS
+    use_c = n <= 16
     best = None
     layers = 2
     while True:
         t = time.perf_counter()
-        sizes, rc, _ = native.growth(n, gens, max_layers=layers)
+        if use_c:
+            sizes, rc, _ = native.growth(n, gens, max_layers=layers, start=start)
+        else:
+            layers_found, complete = bfs_set.bfs_layers(n, gens, max_layers=layers, start=start)
+            sizes, rc = [len(x) for x in layers_found], 0 if complete else 1
         dt = time.perf_counter() - t
         expanded = sum(sizes[:-1]) if rc == 1 else sum(sizes)
         best = (layers, expanded, dt, sizes)
@@ -182,8 +194,8 @@ def cpu_baseline(workload: dict, budget_s: float, host: dict):
         "cpu_model": host["cpu_model"],
         "kind": "oracle",
         "sample": f"first {layers} layers of the same workload ({expanded} states expanded, {sum(sizes)} "
-                  f"states in its hash set, {dt:.1f} s); 1 of {host['nproc']} cores, single-threaded C "
-                  f"hash-set BFS",
+                  f"states in its hash set, {dt:.1f} s); 1 of {host['nproc']} cores, single-threaded "
+                  + ("C hash-set BFS" if use_c else "Python set BFS (the C oracle packs 4 bits per entry)"),
     }
 
 
@@ -214,6 +226,8 @@ def growth_leg(name: str, steps: int, warmup: int) -> dict:
     bitmask = wl.get("bitmask", False)
     run_kw = dict(max_layers=512, keep_all_layers=wl["keep_all"], max_frontier=wl["max_frontier"],
                   bitmask=bitmask)
+    if wl.get("binary_start"):
+        run_kw.update(start=I.binary_central_state(n), max_layers=4096)
     for _ in range(warmup):
         eng.run(n, gens, **run_kw)
     torch.cuda.synchronize()
@@ -224,7 +238,9 @@ def growth_leg(name: str, steps: int, warmup: int) -> dict:
     sizes = results[0].sizes
     for r in results[1:]:
         assert r.sizes == sizes, "growth differs between steps"
-    if wl["family"] in ("pancake", "coxeter") and wl["max_frontier"] is None:
+    if wl.get("binary_start"):
+        assert sum(sizes) == math.comb(n, n // 2), "layer sizes do not sum to the orbit C(n, n/2)"
+    elif wl["family"] in ("pancake", "coxeter") and wl["max_frontier"] is None:
         assert sum(sizes) == math.factorial(n), "layer sizes do not sum to n!"
     expanded = results[0].states_expanded
     elapsed = t1 - t0

@@ -187,9 +187,10 @@ void launch_unpack_bits(int n, const uint64_t *d_keys, uint64_t count, uint8_t *
 // ---- radix_sort.hip ----------------------------------------------------------
 int sort_passes(int bit_lo, int bit_hi);
 // Sorts keys[0..count) on bits [bit_lo, bit_hi); returns the buffer that
-// holds the result (keys or tmp).
+// holds the result (keys or tmp). balanced: digits of equal widths (within
+// one bit) instead of 8-bit digits from bit_lo up (same number of passes).
 uint64_t *radix_sort(uint64_t *keys, uint64_t *tmp, uint64_t count, int bit_lo,
-                     int bit_hi, PipeWork &w);
+                     int bit_hi, PipeWork &w, bool balanced = false);
 // Expands frontier[0..F) into the 32-bit ranks of the k*F candidates
 // (n <= 12) while counting the digits of every pass, then sorts them on
 // bits [0, rank_bits). Returns buf0 or buf1 (each k*F words). d_gfix

@@ -1061,12 +1061,13 @@ uint64_t expand_sort_status_words(uint64_t F, int k) {
 }
 
 uint64_t *radix_sort(uint64_t *keys, uint64_t *tmp, uint64_t count, int bit_lo, int bit_hi,
-                     PipeWork &w) {
+                     PipeWork &w, bool balanced) {
     if (count <= 1 || bit_lo >= bit_hi) return keys;
     w.ensure_status(sort_status_words(count));
     const ArraySrc src{keys, count};
     // pass 0 reads `keys` and writes `tmp`; then they alternate
-    return run_sort(src, count, tmp, keys, bit_lo, bit_hi, w, false, 8.0 * (double)count, keys);
+    return run_sort(src, count, tmp, keys, bit_lo, bit_hi, w, false, 8.0 * (double)count, keys, false, true,
+                    balanced);
 }
 
 uint32_t *radix_sort32(uint32_t *keys, uint32_t *tmp, uint64_t count, int bit_lo, int bit_hi,
