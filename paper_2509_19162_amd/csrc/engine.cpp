@@ -249,7 +249,11 @@ uint64_t Engine::run_chunked(bool ranked, int n, const uint64_t *Ld, uint64_t F,
     chunk_hist_.stream = stream_;
     chunk_hist_.ensure(kChunkBins * sizeof(uint64_t));
     launch_clear(nullptr, 0, chunk_hist_.as<uint64_t>(), kChunkBins, stream_);
-    launch_prefix_hist(n, ranked, Ld, F, gsel_.as<GenSel>(), k, pshift, chunk_hist_.as<unsigned long long>(), w_);
+    if (binary_)
+        launch_prefix_hist_bits(Ld, F, gsel_.as<uint64_t>(), n, k, pshift, chunk_hist_.as<unsigned long long>(), w_);
+    else
+        launch_prefix_hist(n, ranked, Ld, F, gsel_.as<GenSel>(), k, pshift, chunk_hist_.as<unsigned long long>(),
+                           w_);
     std::vector<uint64_t> h(kChunkBins);
     CG_HIP(hipMemcpyAsync(h.data(), chunk_hist_.p, sizeof(uint64_t) * kChunkBins, hipMemcpyDeviceToHost, stream_));
     CG_HIP(hipStreamSynchronize(stream_));
@@ -276,8 +280,12 @@ uint64_t Engine::run_chunked(bool ranked, int n, const uint64_t *Ld, uint64_t F,
     for (const Chunk &c : chunks) {
         if (!c.count) continue;
         launch_clear(nullptr, 0, w_.counter() + 1, 1, stream_);
-        launch_expand_filter(n, ranked, Ld, F, gsel_.as<GenSel>(), k, pshift, c.lo, c.hi, cand0_.p, c.count, cursor,
-                             w_);
+        if (binary_)
+            launch_expand_filter_bits(Ld, F, gsel_.as<uint64_t>(), n, k, pshift, c.lo, c.hi, cand0_.as<uint64_t>(),
+                                      c.count, cursor, w_);
+        else
+            launch_expand_filter(n, ranked, Ld, F, gsel_.as<GenSel>(), k, pshift, c.lo, c.hi, cand0_.p, c.count,
+                                 cursor, w_);
         uint64_t nj = 0;
         auto part = std::make_unique<DevBuf>();
         part->stream = stream_;
@@ -294,7 +302,7 @@ uint64_t Engine::run_chunked(bool ranked, int n, const uint64_t *Ld, uint64_t F,
             }
         } else {
             uint64_t *c0 = cand0_.as<uint64_t>(), *c1 = cand1_.as<uint64_t>();
-            uint64_t *sorted = radix_sort(c0, c1, c.count, bit_lo, bit_hi, w_);
+            uint64_t *sorted = radix_sort(c0, c1, c.count, bit_lo, bit_hi, w_, binary_);
             uint64_t *scratch = sorted == c0 ? c1 : c0;
             launch_dedup_count(sorted, c.count, Ra, na, Rb, nb, scratch, w_.counter(), w_);
             nj = read_counter();
@@ -311,6 +319,10 @@ uint64_t Engine::run_chunked(bool ranked, int n, const uint64_t *Ld, uint64_t F,
         }
     }
     if (total > room) throw Error(CG_E_DEVICE, "layer size out of range (device error)");
+    // the candidate arrays (the largest buffers) are done with: the new
+    // layer and the chunks' survivors must fit beside the window
+    cand0_.release();
+    cand1_.release();
     if (!dst) {
         lay_[in].ensure(std::max<uint64_t>(total, 1) * sizeof(uint64_t), 1.25);
         dst = lay_[in].as<uint64_t>();
@@ -376,6 +388,7 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
 
     uint64_t written = 0;
     const bool binary = spec.binary;
+    binary_ = binary;
     const uint64_t key0 = binary ? pack_bits_host(n, spec.start) : pack_host(n, spec.start);
     if (binary) {
         // per generator, the byte tables of its bit permutation
@@ -529,8 +542,6 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             }
         }
         const bool chunked = cap < C;
-        if (chunked && binary)
-            throw Error(CG_E_NOMEM, "binary states: a layer's candidates do not fit in device memory (no chunking)");
 
         const uint64_t *Ld, *Lp;
         uint64_t *out;

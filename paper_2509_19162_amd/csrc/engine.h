@@ -57,6 +57,7 @@ private:
                       uint64_t &written);
     uint64_t forced_chunk(uint64_t C);
     uint64_t chunk_capacity(uint64_t C, size_t key_bytes);
+    bool binary_ = false;  // the current run's states are binary (one bit per entry)
     uint64_t run_chunked(bool ranked, int n, const uint64_t *Ld, uint64_t F, const uint64_t *Ra, uint64_t na,
                          const uint64_t *Rb, uint64_t nb, int k, uint64_t cap, int rank_bits, int bit_lo, int bit_hi,
                          uint64_t *dst, uint64_t out_cap, uint64_t room, int in);

@@ -183,6 +183,14 @@ std::vector<uint64_t> make_bit_tables(int n, const uint8_t *gens, int k);
 void launch_expand_bits(const uint64_t *frontier, uint64_t F, const uint64_t *d_tables, int n, int k,
                         uint64_t *out, PipeWork &w);
 void launch_unpack_bits(int n, const uint64_t *d_keys, uint64_t count, uint8_t *d_rows, hipStream_t s);
+// Key-range chunks of binary candidates: counts per range (key >> pshift,
+// kChunkBins ranges) into d_hist, and the candidates of ranges [blo, bhi)
+// appended to out through *cursor (at most cap; an overrun sets error bit 8).
+void launch_prefix_hist_bits(const uint64_t *frontier, uint64_t F, const uint64_t *d_tables, int n, int k,
+                             int pshift, unsigned long long *d_hist, PipeWork &w);
+void launch_expand_filter_bits(const uint64_t *frontier, uint64_t F, const uint64_t *d_tables, int n, int k,
+                               int pshift, uint32_t blo, uint32_t bhi, uint64_t *out, uint64_t cap,
+                               unsigned long long *cursor, PipeWork &w);
 
 // ---- radix_sort.hip ----------------------------------------------------------
 int sort_passes(int bit_lo, int bit_hi);

@@ -135,3 +135,28 @@ def test_batches_and_queue_refuse_binary_states():
         with pytest.raises(api.CGError) as e:
             q.submit(n, I.lrx(n), start=s)
         assert e.value.code == N.CG_E_UNSUPPORTED
+
+
+def test_binary_chunked_layers(monkeypatch):
+    """Key-range chunks of binary candidates (forced small) give the same
+    layers: reversal cosets against the closed form, LRX against the
+    oracle."""
+    n = 24
+    monkeypatch.setenv("CG_CHUNK_CANDIDATES", "50000000")
+    r = api.growth_ex(n, I.reversals(n), start=I.binary_central_state(n), max_layers=64)
+    assert r.sizes == binary_coset_growth(n)
+    monkeypatch.setenv("CG_CHUNK_CANDIDATES", "5000")
+    s = I.binary_central_state(20)
+    r = api.growth_ex(20, I.lrx(20), start=s, max_layers=4096, export_layers=200_000)
+    layers, _ = bfs_set.bfs_layers(20, I.lrx(20), start=s)
+    assert r.sizes == [len(x) for x in layers]
+    for got, exp in zip(r.layers, layers):
+        assert np.array_equal(got, np.array(sorted(exp), dtype=np.uint8).reshape(-1, 20))
+
+
+def test_reversal_cosets_n30_chunked_by_memory():
+    """n = 30: 435 reversals on the central state; the largest layer's
+    1.8e10 candidates do not fit at once and run in key-range chunks."""
+    n = 30
+    r = api.growth_ex(n, I.reversals(n), start=I.binary_central_state(n), max_layers=64)
+    assert r.sizes == binary_coset_growth(n)
