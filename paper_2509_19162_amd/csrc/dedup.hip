@@ -46,7 +46,14 @@ constexpr int kTile = kBlock * kIpt;  // 4096 candidates per dedup tile by defau
 #define CG_GATHER_TILES 4
 #endif
 constexpr int kGatherTiles = CG_GATHER_TILES;  // dedup tiles per gather block
-constexpr int kRefIpt = 4;            // reference keys per thread loaded with the tile
+// reference keys per thread loaded with the tile and searched in lockstep:
+// kRefIptFew, or kRefIptMany when the references average more than
+// kRefManyAt per thread (about 32/k of them for k generators: S_16 LRX,
+// k = 3, set difference and compaction 154 -> 142 ms with 8; with 11
+// generators 4 is faster, 11.2 against 13.1 ms on S_12 pancake)
+constexpr int kRefIptFew = 4;
+constexpr int kRefIptMany = 8;
+constexpr uint64_t kRefManyAt = 6;
 #ifndef CG_DEDUP_LOCKSTEP
 #define CG_DEDUP_LOCKSTEP 1  // the tile's first references searched in lockstep
 #endif
@@ -163,7 +170,7 @@ __global__ __launch_bounds__(256) void mark_refs_kernel(P pol, const typename P:
     }
 }
 
-template <class P>
+template <class P, int kRefIpt>
 __global__ __launch_bounds__(kBlock) void dedup_local_kernel(
     P pol, const typename P::K *__restrict__ S, uint64_t C, const typename P::Ref *__restrict__ A, uint64_t na,
     const typename P::Ref *__restrict__ B, uint64_t nb, const uint64_t *__restrict__ bounds,
@@ -455,8 +462,14 @@ void dedup_count_impl(P pol, const typename P::K *sorted, uint64_t C, const type
                            pol, sorted, C, a, na, b, nb, w.bounds.as<uint64_t>(), ntiles);
         CG_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(dedup_local_kernel<P>, dim3(ntiles), dim3(kBlock), 0, w.stream, pol, sorted, C, a,
-                       na, b, nb, w.bounds.as<const uint64_t>(), gkill, tmp, w.tile_cnt.as<uint32_t>());
+    // references per thread of an average tile
+    const bool many = !gkill && (na + nb) * (uint64_t)kTile > kRefManyAt * kBlock * C;
+    if (many)
+        hipLaunchKernelGGL((dedup_local_kernel<P, kRefIptMany>), dim3(ntiles), dim3(kBlock), 0, w.stream, pol, sorted,
+                           C, a, na, b, nb, w.bounds.as<const uint64_t>(), gkill, tmp, w.tile_cnt.as<uint32_t>());
+    else
+        hipLaunchKernelGGL((dedup_local_kernel<P, kRefIptFew>), dim3(ntiles), dim3(kBlock), 0, w.stream, pol, sorted,
+                           C, a, na, b, nb, w.bounds.as<const uint64_t>(), gkill, tmp, w.tile_cnt.as<uint32_t>());
     CG_HIP(hipGetLastError());
     hipLaunchKernelGGL(count_scan_kernel, dim3(nscan), dim3(kScanBlock), 0, w.stream,
                        w.tile_cnt.as<const uint32_t>(), ntiles, w.tile_off.as<uint64_t>(), d_count,
