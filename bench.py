@@ -5,7 +5,7 @@ difference against layers d and d-1, compaction) over one growth job.
 Inputs are synthetic by nature (the generators of the paper's families);
 each job's start state is resident on the device before the timed region.
 
-Default run (the default line): the headline is S_16 with the L, R, X
+Default run (one JSON line): the headline is S_16 with the L, R, X
 generators, every layer up to the first one larger than 2^31 (about 1e10
 states, 44 layers): states expanded per second over K timed growths, with
 the roofline of the dominant kernel (HIP events over the timed region) and
@@ -19,7 +19,7 @@ bandwidth as the measured HBM ceiling.
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 
 --workload picks one leg alone (lrx16, pancake12, coxeter8, pancake13,
-coxeter14, batch4096, serving).
+coxeter14, coset38, batch4096, serving).
 """
 
 from __future__ import annotations

@@ -25,7 +25,7 @@
  * call (the queue copies what it needs before cg_queue_submit returns).
  * Output arrays are caller-owned host memory. Device memory is owned by the
  * library; it goes back to the library's device arena when a call returns
- * (queue: when a job retires) and to the driver on
+ * (queue: when a job retires) and to HIP (hipFree) on
  * cg_release_cached_memory().
  */
 #ifndef CAYLEYGROWTH_H
@@ -370,7 +370,7 @@ int cg_queue_stats(cg_queue_t *q, cg_queue_stats_t *out);
  * reused only after the work queued on its last stream has finished. This
  * frees the buffers and graphs that cg_growth_batch keeps between calls (a
  * batch call in progress finishes first; the next one builds them again),
- * then returns the arena to the driver if no buffer is in use (engines and
+ * then frees the arena (hipFree) if no buffer is in use (engines and
  * queues still alive keep theirs).
  */
 void cg_release_cached_memory(void);

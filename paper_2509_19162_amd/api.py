@@ -302,7 +302,7 @@ def growth_batch_noalloc(jobs, max_layers: int = 256, stream=None,
 
 def release_cached_memory() -> None:
     """Frees the buffers that batches keep between calls, then returns the
-    library's device arena to the driver when no buffer uses it
+    library's device arena to HIP (hipFree) when no buffer uses it
     (``cg_release_cached_memory``)."""
     N.lib().cg_release_cached_memory()
 

@@ -120,7 +120,7 @@ struct DevBuf {
     T *as() const { return static_cast<T *>(p); }
 };
 
-// Returns the device arena to the driver when no buffer uses it
+// Frees the device arena (hipFree) when no buffer uses it
 // (cg_release_cached_memory).
 void release_cached_device_memory();
 // Makes [p, p + bytes) the current device's arena (p == nullptr: back to an
@@ -270,7 +270,7 @@ void launch_expand_ranked(int n, const uint64_t *frontier, uint64_t F, const Gen
 // True once the device's arena exists (buffers then grow to exact sizes).
 bool arena_active();
 // Largest block a DevBuf could get now: the arena's largest free range, or
-// the driver's free memory when no arena exists.
+// the device's free memory (hipMemGetInfo) when no arena exists.
 size_t device_bytes_available();
 
 // ---- key-range chunks (chunk.hip) ----

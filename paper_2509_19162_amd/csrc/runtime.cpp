@@ -21,7 +21,7 @@ void hip_check(hipError_t e, const char *what, const char *file, int line) {
 }
 
 // ---------------------------------------------------------------------------
-// Device arena. On this driver a hipMalloc is fast while little memory is
+// Device arena. On this HIP runtime a hipMalloc is fast while little memory is
 // held, but a large one takes seconds once tens of GB are already held. So
 // the first large request reserves one big region (CG_ARENA_FRACTION of the
 // free memory, default 0.85; 0 disables it) and every buffer is carved out

@@ -148,7 +148,7 @@ def _stored_batch():
 def test_release_frees_the_buffers_batches_keep(oracle_c):
     """cg_release_cached_memory also frees what batches keep between calls
     (the small-job runner's buffers and launch graph), so the device arena
-    goes back to the driver; the next batch builds its graph again and
+    is freed (hipFree); the next batch builds its graph again and
     gives the same results."""
     import torch
 
