@@ -231,10 +231,12 @@ def growth_leg(name: str, steps: int, warmup: int) -> dict:
     for _ in range(warmup):
         eng.run(n, gens, **run_kw)
     torch.cuda.synchronize()
+    api.memory_stats(reset_peak=True)
     t0 = time.perf_counter()
     results = [eng.run(n, gens, profile=not bitmask, **run_kw) for _ in range(steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    mem = api.memory_stats()
     sizes = results[0].sizes
     for r in results[1:]:
         assert r.sizes == sizes, "growth differs between steps"
@@ -251,6 +253,9 @@ def growth_leg(name: str, steps: int, warmup: int) -> dict:
         "n": n, "generators": len(gens), "layers": len(sizes), "states": sum(sizes),
         "states_expanded_per_step": expanded, "candidates_per_step": results[0].candidates,
         "sizes": sizes, "desc": wl["desc"], "bitmask": bitmask,
+        # the most device memory the library's buffers held during the
+        # timed growths (layers, candidates, pipeline scratch)
+        "device_memory": {"peak_held_bytes": mem["peak_held_bytes"], "arena_bytes": mem["arena_bytes"]},
     }
     agg = agg_kstats(results)
     if agg:
@@ -596,6 +601,7 @@ def _growth_line(name: str, leg: dict, steps: int, warmup: int, cpu) -> dict:
         "cpu_baseline": cpu,
         "kernel_ms_per_step": leg.get("kernel_ms_per_step"),
         "pipeline": leg.get("pipeline"),
+        "device_memory": leg.get("device_memory"),
     }
 
 
@@ -689,7 +695,7 @@ def main():
         line["pancake12"] = {k: p12[k] for k in ("value", "ms_per_step", "steps", "states", "layers")}
         line["pancake12"].update({"unit": "states/s", "workload": p12["desc"], "roofline": p12.get("roofline"),
                                   "kernel_ms_per_step": p12.get("kernel_ms_per_step"),
-                                  "pipeline": p12.get("pipeline"),
+                                  "pipeline": p12.get("pipeline"), "device_memory": p12.get("device_memory"),
                                   "paper_context": {"s12_pancake_full_growth_s": PAPER_PANCAKE12_SECONDS,
                                                     "hardware": "Kaggle CPU (another machine; context only)"}})
         api.release_cached_memory()

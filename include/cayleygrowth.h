@@ -376,6 +376,25 @@ int cg_queue_stats(cg_queue_t *q, cg_queue_stats_t *out);
 void cg_release_cached_memory(void);
 
 /*
+ * Device memory of the library, for callers that size budgets or report
+ * footprints (the paper's growth benchmarks state the memory a run needs).
+ *   held_bytes       bytes its device buffers hold now (all devices;
+ *                    engines, queues, batches, pipeline scratch)
+ *   peak_held_bytes  the most they held at once since the last reset
+ *   arena_bytes      device memory reserved as arenas (the buffers are
+ *                    carved out of it; a caller's workspace not included)
+ * The static array of cg_growth_batch_noalloc (64 MiB per device) is not
+ * counted. reset_peak != 0 restarts the peak at the current value after
+ * filling *out. Returns CG_OK or CG_E_INVAL (NULL out).
+ */
+typedef struct cg_memory_stats {
+    uint64_t held_bytes;
+    uint64_t peak_held_bytes;
+    uint64_t arena_bytes;
+} cg_memory_stats_t;
+int cg_memory_stats(cg_memory_stats_t *out, int reset_peak);
+
+/*
  * Hands the library device memory to carve its buffers from (for example a
  * tensor the caller allocated with PyTorch), on the current device:
  * dev_ptr..dev_ptr+bytes becomes the arena; requests it cannot hold fall

@@ -126,6 +126,14 @@ class CgQueueStats(ctypes.Structure):
     ]
 
 
+class CgMemoryStats(ctypes.Structure):
+    _fields_ = [
+        ("held_bytes", ctypes.c_uint64),
+        ("peak_held_bytes", ctypes.c_uint64),
+        ("arena_bytes", ctypes.c_uint64),
+    ]
+
+
 class CgGrowthStats(ctypes.Structure):
     _fields_ = [
         ("total", ctypes.c_uint64),
@@ -168,6 +176,7 @@ SIGNATURES = [
     ("cg_queue_cancel", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     ("cg_queue_destroy", None, [ctypes.c_void_p]),
     ("cg_queue_stats", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CgQueueStats)]),
+    ("cg_memory_stats", ctypes.c_int, [ctypes.POINTER(CgMemoryStats), ctypes.c_int]),
     ("cg_release_cached_memory", None, []),
     ("cg_set_workspace", ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t]),
     ("cg_growth_stats", ctypes.c_int, [u64p, ctypes.c_int, ctypes.POINTER(CgGrowthStats)]),

@@ -307,6 +307,14 @@ def release_cached_memory() -> None:
     N.lib().cg_release_cached_memory()
 
 
+def memory_stats(reset_peak: bool = False) -> Dict[str, int]:
+    """Bytes the library's device buffers hold now and at most since the
+    last reset, and the arenas' reserved size (``cg_memory_stats``)."""
+    st = N.CgMemoryStats()
+    _check(N.lib().cg_memory_stats(ctypes.byref(st), 1 if reset_peak else 0))
+    return {f: int(getattr(st, f)) for f, _ in N.CgMemoryStats._fields_}
+
+
 _WORKSPACE = None  # keeps the caller's tensor alive while the library uses it
 
 

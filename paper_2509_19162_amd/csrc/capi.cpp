@@ -96,6 +96,14 @@ int cg_growth(int n, const uint8_t *gens, int n_gens, int max_layers, uint64_t *
     return cg_growth_ex(&job, &res, nullptr);
 }
 
+int cg_memory_stats(cg_memory_stats_t *out, int reset_peak) {
+    return guarded([&]() -> int {
+        if (!out) throw cg::Error(CG_E_INVAL, "NULL result");
+        cg::memory_stats(out, reset_peak != 0);
+        return CG_OK;
+    });
+}
+
 int cg_set_workspace(void *dev_ptr, size_t bytes) {
     return guarded([&]() -> int {
         cg::release_batch_buffers();  // the batches' kept buffers may live in the old arena

@@ -120,6 +120,9 @@ struct DevBuf {
     T *as() const { return static_cast<T *>(p); }
 };
 
+// cg_memory_stats: bytes held by the library's device buffers now and at
+// most since the last reset, and the arenas' reserved size.
+void memory_stats(cg_memory_stats_t *out, bool reset_peak);
 // Frees the device arena (hipFree) when no buffer uses it
 // (cg_release_cached_memory).
 void release_cached_device_memory();

@@ -1,6 +1,7 @@
 // Host runtime pieces: HIP error mapping, device buffers, look-back epochs,
 // HIP-event kernel profiling.
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <iterator>
@@ -200,6 +201,32 @@ size_t device_bytes_available() {
     return free_b;
 }
 
+namespace {
+// bytes held by every DevBuf of the process (all devices), and the most
+// they held at once since the last reset
+std::atomic<uint64_t> g_held{0}, g_peak_held{0};
+
+void count_held(uint64_t add) {
+    const uint64_t now = g_held.fetch_add(add) + add;
+    uint64_t pk = g_peak_held.load();
+    while (now > pk && !g_peak_held.compare_exchange_weak(pk, now)) {
+    }
+}
+}  // namespace
+
+void memory_stats(cg_memory_stats_t *out, bool reset_peak) {
+    out->held_bytes = g_held.load();
+    out->peak_held_bytes = g_peak_held.load();
+    uint64_t reserved = 0;
+    {
+        std::lock_guard<std::mutex> lk(arenas().mu);
+        for (auto &kv : arenas().arena)
+            if (kv.second.base && !kv.second.external) reserved += kv.second.size;
+    }
+    out->arena_bytes = reserved;
+    if (reset_peak) g_peak_held.store(g_held.load());
+}
+
 bool DevBuf::ensure(size_t need, double slack) {
     if (need <= bytes && p) return false;
     const size_t old = bytes;
@@ -230,6 +257,7 @@ bool DevBuf::ensure(size_t need, double slack) {
     }
     p = q;
     bytes = want;
+    count_held(want);
     return true;
 }
 
@@ -247,6 +275,7 @@ void DevBuf::release() {
         } else {
             (void)hipFree(p);  // a block of its own; synchronises the device
         }
+        g_held.fetch_sub(bytes);
     }
     p = nullptr;
     bytes = 0;

@@ -252,3 +252,22 @@ def test_growth_from_several_host_threads(oracle_c):
     for (n, g), runs in zip(jobs, got):
         exp = oracle_c.growth(n, g)[0]
         assert runs == [exp] * 3, n
+
+
+def test_memory_stats_track_the_buffers_of_a_run():
+    """cg_memory_stats: the peak covers what a growth needs (S_12 pancake with
+    every layer kept holds all 12! packed states, 3.83 GB), and the bytes
+    held go back down when the engine is closed."""
+    import gc
+    gc.collect()
+    before = api.memory_stats(reset_peak=True)
+    eng = api.Engine()
+    r = eng.run(12, I.pancake(12), max_layers=512, keep_all_layers=True)
+    assert sum(r.sizes) == 479001600
+    during = api.memory_stats()
+    assert during["peak_held_bytes"] >= before["held_bytes"] + 8 * 479001600
+    assert during["held_bytes"] >= before["held_bytes"]
+    eng.close()
+    after = api.memory_stats()
+    assert after["held_bytes"] <= before["held_bytes"] + (64 << 20)
+    assert after["peak_held_bytes"] == during["peak_held_bytes"]
