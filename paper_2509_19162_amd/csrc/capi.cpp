@@ -264,6 +264,24 @@ int cg_test_sort(uint64_t *d_keys, uint64_t *d_tmp, uint64_t count, int bit_lo, 
     });
 }
 
+int cg_test_sort_below(uint64_t *d_keys, uint64_t *d_tmp, uint64_t count, int key_bits, void *stream) {
+    return guarded([&]() -> int {
+        if (key_bits < 1 || key_bits > 64) throw cg::Error(CG_E_INVAL, "key_bits out of 1..64");
+        if (count && (!d_keys || !d_tmp)) throw cg::Error(CG_E_INVAL, "NULL device pointer");
+        hipStream_t s = (hipStream_t)stream;
+        cg::PipeWork w;
+        w.init(s);
+        uint64_t *res = cg::radix_sort(d_keys, d_tmp, count, 0, key_bits, w, true);
+        if (res != d_keys)
+            CG_HIP(hipMemcpyAsync(d_keys, res, count * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+        uint32_t err = 0;
+        CG_HIP(hipMemcpyAsync(&err, w.err(), sizeof err, hipMemcpyDeviceToHost, s));
+        CG_HIP(hipStreamSynchronize(s));
+        if (err) throw cg::Error(CG_E_DEVICE, "kernel error flag set (look-back bound or offset check)");
+        return CG_OK;
+    });
+}
+
 int cg_test_sort32(uint32_t *d_keys, uint32_t *d_tmp, uint64_t count, int bit_lo, int bit_hi,
                    void *stream) {
     return guarded([&]() -> int {

@@ -58,6 +58,16 @@ def sort(keys, bit_lo: int, bit_hi: int, stream=None):
     return keys
 
 
+def sort_below(keys, key_bits: int, stream=None):
+    """Sorted in place on bits [0, key_bits) in digits of balanced widths
+    (the sort of 64-bit ranks and of binary states)."""
+    import torch
+
+    tmp = torch.empty_like(keys)
+    _check(N.lib().cg_test_sort_below(_dptr(keys), _dptr(tmp), keys.numel(), key_bits, _stream(stream)))
+    return keys
+
+
 def sort32(keys, bit_lo: int, bit_hi: int, stream=None):
     """32-bit keys (an int32 tensor holding the bit patterns), sorted in place."""
     import torch

@@ -120,6 +120,37 @@ def test_sort_large_persistent_blocks(count, lo, hi):
     assert np.array_equal(T.to_u64(t), _stable_sorted(keys, lo, hi))
 
 
+# Keys below 2^b sorted on all their bits in digits of balanced widths (the
+# sort of 64-bit ranks and of binary states; 9 bits: two passes of 5 and 4).
+SORT_BELOW_SIZES = [0, 1, 2, 65, 12287, 12288, 12289, 3 * 12288 + 5, 100_003, 1_048_613]
+
+
+@pytest.mark.parametrize("count", SORT_BELOW_SIZES)
+@pytest.mark.parametrize("bits", [8, 9, 17, 33, 38, 45, 48, 49, 64])
+def test_sort_below_matches_numpy(count, bits, rng):
+    if bits == 64:
+        keys = rng.integers(0, 2 ** 63, size=count, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, size=count, dtype=np.uint64)
+    else:
+        keys = rng.integers(0, 2 ** bits, size=count, dtype=np.uint64)
+    if count > 3:
+        keys[:3] = [0, (1 << bits) - 1, (1 << bits) - 1]  # the extremes, one repeated
+    t = T.from_u64(keys)
+    T.sort_below(t, bits)
+    assert np.array_equal(T.to_u64(t), np.sort(keys))
+
+
+@pytest.mark.parametrize("count,bits", [(30_000_017, 45), (7_000_001, 38)])
+def test_sort_below_large_persistent_blocks(count, bits):
+    # 2441 and 570 tiles of 12288 keys against ~512 resident blocks: blocks
+    # take several tiles each, and load the next one while writing one out
+    rng = np.random.default_rng([count, bits])
+    keys = rng.integers(0, 2 ** bits, size=count, dtype=np.uint64)
+    keys[rng.integers(0, count, size=count // 3)] = keys[0]  # a heavy digit in every pass
+    t = T.from_u64(keys)
+    T.sort_below(t, bits)
+    assert np.array_equal(T.to_u64(t), np.sort(keys))
+
+
 def test_sort32_large():
     rng = np.random.default_rng(32)
     keys = rng.integers(0, 479001600, size=30_000_001, dtype=np.uint64).astype(np.uint32)

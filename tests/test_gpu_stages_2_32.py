@@ -76,6 +76,23 @@ def test_sort64_beyond_2_32_keys():
         assert torch.equal(keys[s:e], exp), s
 
 
+def test_sort64_balanced_digits_beyond_2_32_keys():
+    """The same keys sorted on bits [0, 33) in balanced digits (7,7,7,6,6),
+    as the sorts of 64-bit ranks and binary states run."""
+    print("64-bit sort in balanced digits of", N_KEYS, "scrambled keys", flush=True)
+    keys = _scramble(N_KEYS)
+    tmp = torch.empty_like(keys)
+    rc = N.lib().cg_test_sort_below(T._dptr(keys), T._dptr(tmp), N_KEYS, 33, T._stream(None))
+    assert rc == N.CG_OK, N.lib().cg_last_error()
+    del tmp
+    N.lib().cg_release_cached_memory()
+    torch.cuda.synchronize()
+    for s in range(0, N_KEYS, SLICE):
+        e = min(N_KEYS, s + SLICE)
+        exp = torch.arange(s, e, dtype=torch.int64, device="cuda")
+        assert torch.equal(keys[s:e], exp), s
+
+
 def test_sort32_beyond_2_32_keys():
     print("32-bit sort of", N_KEYS, "keys with", DELTA, "repeated values", flush=True)
     keys = _scramble(N_KEYS, torch.int32)
