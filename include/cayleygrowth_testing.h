@@ -55,7 +55,7 @@ int cg_test_sort(uint64_t *d_keys, uint64_t *d_tmp, uint64_t count,
 
 /*
  * Stable sort of d_keys[0..count) on bits [0, key_bits) (1 <= key_bits <=
- * 64) in digits of balanced widths (45 bits: 8,8,8,7,7,7): the sort the
+ * 64) in digits of balanced widths (45 bits: 7,7,7,8,8,8): the sort the
  * growth step runs on 64-bit lexicographic ranks (n = 13..16) and on binary
  * states, whose keys are all below 2^key_bits. The result is left in
  * d_keys; d_tmp holds count keys.

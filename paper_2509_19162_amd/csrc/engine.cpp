@@ -634,7 +634,7 @@ void Engine::run(const JobSpec &spec, cg_result_t *res) {
             const uint64_t *sorted;
             if (binary) {
                 launch_expand_bits(Ld, F, gsel_.as<uint64_t>(), n, k, cand0_.as<uint64_t>(), w_);
-                // the n key bits in balanced digits (38 bits: 8,8,8,7,7)
+                // the n key bits in balanced digits (38 bits: 7,7,8,8,8)
                 sorted = radix_sort(cand0_.as<uint64_t>(), cand1_.as<uint64_t>(), C, bit_lo, bit_hi, w_, true);
             } else {
                 sorted = expand_sort(Ld, F, gsel_.as<GenSel>(), k, cand0_.as<uint64_t>(), cand1_.as<uint64_t>(),

@@ -43,15 +43,15 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
 // Keys per thread: 30 for 32-bit keys (512 threads, 15360-key tiles), 16
-// for 64-bit keys (768 threads, below). A pass is bound by the keys in
-// flight over a tile's latency, about half of which is the wait for the
-// predecessors' look-back words (measured per tile with the real-time
-// clock: 6 us load and rank, 11 us look-back, 5.5 us reorder and scatter
-// for 64-bit keys; a window of 12 predecessors per round instead of 1 + 3
-// did not shorten it, so the wait is the words' latency between XCDs, not
-// the walk). 30 keys, their packed ranks and the look-back fit 80 VGPRs,
-// which with the split LDS reorder below keeps 3 tiles resident per CU
-// (32 keys need 88 VGPRs: 2).
+// for 64-bit keys (768 threads, below). Measured per tile with the
+// real-time clock, a 64-bit tile spends 6 us loading and ranking, 11 us
+// waiting for its predecessors' look-back words and 5.5 us reordering and
+// writing. The wait is not the chain's own latency: wider look-back
+// windows, and independent chains over segments of the keys, left the
+// pass time as it was (or slowed it); it fills the time of the tiles in
+// flight while the writes of the digit runs set the pace. 30 keys, their
+// packed ranks and the look-back fit 80 VGPRs, which with the split LDS
+// reorder below keeps 3 tiles resident per CU (32 keys need 88 VGPRs: 2).
 #ifndef CG_SORT_IPT32
 #define CG_SORT_IPT32 30
 #endif
@@ -294,6 +294,16 @@ __device__ __forceinline__ uint32_t expand_slot(int j) {
 #define CG_HIST_DIRECT_PASSES 1
 #endif
 
+// Balanced digits: the last `extra` of the P passes take the one bit more
+// (S_16: 45 bits as 7,7,7,8,8,8: sort passes 634 -> 616 ms against
+// 8,8,8,7,7,7; S_12 ranks and binary states measured the same either way).
+#ifndef CG_RANK_WIDE_LAST
+#define CG_RANK_WIDE_LAST 1
+#endif
+__host__ __device__ constexpr bool wide_pass(int p, int P, int extra) {
+    return CG_RANK_WIDE_LAST ? p >= P - extra : p < extra;
+}
+
 // Bits of the ranks of S_N (the smallest b with 2^b >= N!) and the sort
 // passes over them, fixed at compile time for the ranked expand.
 template <int N>
@@ -309,13 +319,13 @@ struct RankPasses {
         return b;
     }
     static constexpr int passes = (bits() + kRadixBits - 1) / kRadixBits;
-    // Balanced digits: the first bits() % passes passes take one bit more
-    // (S_16: 45 bits as 8,8,8,7,7,7 rather than 8,8,8,8,8,5). A digit of
-    // fewer bits leaves longer runs per tile, and the passes cost less in
-    // sum: S_16 LRX sort passes 676 -> 655 ms. make_passes(.., true) lays
-    // out the same passes.
+    // Balanced digits: bits() % passes of the passes take one bit more
+    // (wide_pass; S_16: 45 bits as 7,7,7,8,8,8 rather than 8,8,8,8,8,5). A
+    // digit of fewer bits leaves longer runs per tile, and the passes cost
+    // less in sum: S_16 LRX sort passes 676 -> 655 ms. make_passes(.., true)
+    // lays out the same passes.
     static constexpr int width(int p) {
-        return passes == 0 ? 0 : bits() / passes + (p < bits() % passes ? 1 : 0);  // S_1: no passes
+        return passes == 0 ? 0 : bits() / passes + (wide_pass(p, passes, bits() % passes) ? 1 : 0);  // S_1: no passes
     }
     static constexpr int shift(int p) { return p == 0 ? 0 : shift(p - 1) + width(p - 1); }
     static constexpr uint32_t mask(int p) { return (1u << width(p)) - 1u; }
@@ -889,7 +899,7 @@ PassDesc make_passes(int bit_lo, int bit_hi, bool balanced = false) {
         const int P = (b + kRadixBits - 1) / kRadixBits;
         int s = bit_lo;
         for (int p = 0; p < P; ++p) {
-            const int bits = b / P + (p < b % P ? 1 : 0);
+            const int bits = b / P + (wide_pass(p, P, b % P) ? 1 : 0);
             pd.shift[p] = s;
             pd.mask[p] = (1u << bits) - 1u;
             s += bits;

@@ -121,7 +121,7 @@ def test_sort_large_persistent_blocks(count, lo, hi):
 
 
 # Keys below 2^b sorted on all their bits in digits of balanced widths (the
-# sort of 64-bit ranks and of binary states; 9 bits: two passes of 5 and 4).
+# sort of 64-bit ranks and of binary states; 9 bits: two passes of 4 and 5).
 SORT_BELOW_SIZES = [0, 1, 2, 65, 12287, 12288, 12289, 3 * 12288 + 5, 100_003, 1_048_613]
 
 

@@ -77,7 +77,7 @@ def test_sort64_beyond_2_32_keys():
 
 
 def test_sort64_balanced_digits_beyond_2_32_keys():
-    """The same keys sorted on bits [0, 33) in balanced digits (7,7,7,6,6),
+    """The same keys sorted on bits [0, 33) in balanced digits (6,6,7,7,7),
     as the sorts of 64-bit ranks and binary states run."""
     print("64-bit sort in balanced digits of", N_KEYS, "scrambled keys", flush=True)
     keys = _scramble(N_KEYS)
