@@ -130,6 +130,10 @@ constexpr int kRows = CG_SORT_ROWS;  // rows ranked per LDS round trip
 #ifndef CG_SORT_NT_STORE64
 #define CG_SORT_NT_STORE64 1
 #endif
+// Look-back words only for the values the pass's digit can take
+#ifndef CG_LB_USED_DIGITS
+#define CG_LB_USED_DIGITS 1
+#endif
 #ifndef CG_SORT_HALF_MASK
 #define CG_SORT_HALF_MASK 1  // peer masks set and cleared by 32-bit halves
 #endif
@@ -722,7 +726,10 @@ __global__ __launch_bounds__(TileOf<typename Src::Key>::block) CG_SORT_ATTR void
             const uint32_t pub = run - (d == dmask ? (uint32_t)kTileK - nvalid : 0u);
             uint64_t *my = status + (uint64_t)tile * kRadix + d;
             uint64_t excl = 0;
-            if (tile == 0) {
+            if (CG_LB_USED_DIGITS && d > dmask) {
+                // a value this pass's digit never takes (7-bit digits: the
+                // upper half, two whole waves): no word to publish or read
+            } else if (tile == 0) {
                 lb_store(my, lb_word(epoch, kFlagInclusive, pub));
             } else {
                 lb_store(my, lb_word(epoch, kFlagAggregate, pub));
