@@ -129,6 +129,24 @@ def test_rank64_sampled(n):
         assert sorted(row) == list(range(n)) and _lehmer_rank(row) == v
 
 
+@pytest.mark.parametrize("n", [13, 14, 15, 16])
+def test_unrank64_many_ranks_round_trip(n):
+    """200,000 random ranks below n!: unrank gives a permutation (n distinct
+    nibbles) whose rank (checked against the Lehmer code above) is the rank
+    it came from, so every digit of the split division chain is exact."""
+    rng = np.random.default_rng(2000 + n)
+    rs = np.ascontiguousarray(rng.integers(0, math.factorial(n), size=200_000, dtype=np.uint64))
+    keys = np.zeros(len(rs), dtype=np.uint64)
+    assert N.lib().cg_test_unrank64(n, rs.ctypes.data_as(N.u64p), len(rs), keys.ctypes.data_as(N.u64p), 0,
+                                    None) == 0
+    nib = np.stack([(keys >> np.uint64(4 * (n - 1 - i))) & np.uint64(15) for i in range(n)], axis=1)
+    assert np.array_equal(np.sort(nib, axis=1), np.broadcast_to(np.arange(n, dtype=np.uint64), nib.shape))
+    back = np.zeros(len(rs), dtype=np.uint64)
+    assert N.lib().cg_test_rank64(n, keys.ctypes.data_as(N.u64p), len(rs), back.ctypes.data_as(N.u64p), 0,
+                                  None) == 0
+    assert np.array_equal(back, rs)
+
+
 def test_rank64_rejects_bad_input():
     r = np.zeros(1, dtype=np.uint64)
     k = np.zeros(1, dtype=np.uint64)
