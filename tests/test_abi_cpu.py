@@ -137,3 +137,15 @@ def test_binary_state_jobs_are_validated():
     assert rc == N.CG_E_INVAL and "sort path" in msg
     rc, msg = run(20, half(20), N.CG_START_STATE | N.CG_SMALL_JOB)
     assert rc == N.CG_E_INVAL and "sort path" in msg
+
+
+def test_sort_hooks_validate_before_touching_the_device():
+    """The testing ABI's sorts reject bad bit ranges and null buffers before
+    any device call (so this runs without a GPU)."""
+    lib = N.lib()
+    for kb in (0, 65, -3):
+        assert lib.cg_test_sort_below(None, None, 0, kb, None) == N.CG_E_INVAL
+    assert lib.cg_test_sort_below(None, None, 5, 45, None) == N.CG_E_INVAL
+    assert lib.cg_test_sort(None, None, 0, 8, 4, None) == N.CG_E_INVAL
+    assert lib.cg_test_sort(None, None, 0, 0, 65, None) == N.CG_E_INVAL
+    assert lib.cg_test_sort32(None, None, 0, 0, 33, None) == N.CG_E_INVAL
